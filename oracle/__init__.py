@@ -1,0 +1,28 @@
+"""LSHBloom CPU oracle (test infrastructure only).
+
+A plain sequential reference of the LSHBloom hot path, written in C
+(`lshbloom_oracle.c`) and wrapped here with ctypes.  Only the tests, the smoke
+check and the benchmark's CPU-baseline leg may import it; the GPU library never
+does, and the two share no code.
+"""
+
+from .oracle import (  # noqa: F401
+    P61,
+    OracleIndex,
+    band_key,
+    build,
+    fmix64,
+    fn_lsh,
+    fp_lsh,
+    lib,
+    minhash_doc,
+    optimal_br,
+    p_band_from_eff,
+    p_eff_from_band,
+    params,
+    perm,
+    positions,
+    sha1,
+    shingle_hash,
+    splitmix64_stream,
+)

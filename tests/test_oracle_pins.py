@@ -1,0 +1,414 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+None of these re-derive the oracle's own code: each compares it with a
+library routine (hashlib, Python big integers, scipy quadrature), a published
+test vector, a value printed in the paper, a closed form, or a statistical law
+of the method (MinHash estimator, LSH S-curve, Bloom false-positive law).
+"""
+
+import hashlib
+import json
+import math
+import os
+import struct
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+P61 = (1 << 61) - 1
+
+
+def _golden(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- SHA-1 ----
+
+def test_sha1_published_vectors():
+    for v in _golden("hash_vectors.json")["sha1"]:
+        assert oracle.sha1(v["message_ascii"].encode()).hex() == v["digest_hex"], v["cite"]
+
+
+@pytest.mark.parametrize("n", [0, 1, 4, 19, 20, 52, 55, 56, 57, 63, 64, 65, 119, 120, 128, 300])
+def test_sha1_matches_hashlib(n):
+    rng = np.random.default_rng(n)
+    msg = rng.integers(0, 256, n, dtype=np.uint8).tobytes()
+    assert oracle.sha1(msg) == hashlib.sha1(msg).digest()
+
+
+def test_shingle_hash_is_first_four_digest_bytes_le():
+    rng = np.random.default_rng(7)
+    for ln in [1, 2, 3, 4, 5, 7, 13, 20]:
+        for _ in range(20):
+            tok = rng.integers(0, 2**32, ln, dtype=np.uint64).astype(np.uint32)
+            want = struct.unpack("<I", hashlib.sha1(tok.astype("<u4").tobytes()).digest()[:4])[0]
+            assert oracle.shingle_hash(tok) == want
+
+
+# ------------------------------------------------------------ SplitMix64 ----
+
+def test_splitmix64_published_vector():
+    v = _golden("hash_vectors.json")["splitmix64"]
+    assert oracle.splitmix64_stream(v["seed"], len(v["outputs"])) == v["outputs"]
+
+
+def test_coefficients_follow_the_seed_stream():
+    idx = oracle.OracleIndex(8, 2, 4, 1000, 1e-3, seed=1234567)
+    a, b, salts = idx.coeffs()
+    stream = oracle.splitmix64_stream(1234567, 64)
+    tops = [s >> 3 for s in stream]
+    # draws are consumed in order a_0..a_7, b_0..b_7, then three salts; the
+    # rejection of 0 or >= 2^61-1 has probability ~2^-61 so none occurs here
+    assert all(1 <= t < P61 for t in tops[:16])
+    assert [int(x) for x in a] == tops[:8]
+    assert [int(x) for x in b] == tops[8:16]
+    assert salts == stream[16:19]
+
+
+# ------------------------------------------------- permutation arithmetic ----
+
+def test_perm_matches_big_integers():
+    rng = np.random.default_rng(11)
+    cases = [(1, 0, 0), (P61 - 1, P61 - 1, 2**32 - 1), (P61 - 1, 0, 2**32 - 1), (1, P61 - 1, 0),
+             (2**32, 5, 2**32 - 1), (2**61 - 2, 2**61 - 2, 1), ((1 << 60) + 12345, 99, 2**31)]
+    for _ in range(20000):
+        cases.append((int(rng.integers(1, P61)), int(rng.integers(0, P61)), int(rng.integers(0, 2**32))))
+    for a, b, x in cases:
+        assert oracle.perm(a, b, x) == ((a * x + b) % P61) & 0xFFFFFFFF, (a, b, x)
+
+
+def test_perm_hits_canonical_boundary():
+    # a*x + b = p exactly must map to 0, not to p's low word
+    a, x = 1, 0
+    assert oracle.perm(a, P61 - 1, x) == (P61 - 1) & 0xFFFFFFFF
+    # (p-1)*1 + 1 = p -> 0
+    assert oracle.perm(P61 - 1, 1, 1) == 0
+
+
+# --------------------------------------------------------------- MinHash ----
+
+def _brute_sig(tokens, w, a, b):
+    tokens = [int(t) for t in tokens]
+    L = len(tokens)
+    if L == 0:
+        return [0xFFFFFFFF] * len(a)
+    if L >= w:
+        shingles = {tuple(tokens[t:t + w]) for t in range(L - w + 1)}
+    else:
+        shingles = {tuple(tokens)}
+    xs = [struct.unpack("<I", hashlib.sha1(struct.pack("<%dI" % len(s), *s)).digest()[:4])[0] for s in shingles]
+    return [min(((int(ai) * x + int(bi)) % P61) & 0xFFFFFFFF for x in xs) for ai, bi in zip(a, b)]
+
+
+def test_minhash_is_min_over_the_shingle_set():
+    idx = oracle.OracleIndex(16, 4, 4, 1000, 1e-3, seed=99)
+    a, b, _ = idx.coeffs()
+    rng = np.random.default_rng(5)
+    for L in [0, 1, 2, 4, 5, 6, 9, 40, 120]:
+        # a small vocabulary so that shingles repeat inside a document
+        tok = rng.integers(0, 3, L).astype(np.uint32)
+        sig = oracle.minhash_doc(tok, 5, a, b)
+        assert [int(v) for v in sig] == _brute_sig(tok, 5, a, b), L
+
+
+def test_minhash_invariant_to_shingle_order_and_repeats():
+    idx = oracle.OracleIndex(32, 4, 8, 1000, 1e-3, seed=3)
+    a, b, _ = idx.coeffs()
+    rng = np.random.default_rng(8)
+    # documents made of disjoint 5-token blocks separated by a sentinel never
+    # share cross-block shingles beyond the sentinel ones, so reordering the
+    # blocks with each block once more keeps the shingle set when w = 1
+    tok = rng.integers(0, 50000, 200).astype(np.uint32)
+    perm_tok = tok[rng.permutation(200)]
+    doubled = np.concatenate([tok, tok[::-1]])
+    s1 = oracle.minhash_doc(tok, 1, a, b)
+    assert np.array_equal(s1, oracle.minhash_doc(perm_tok, 1, a, b))
+    assert np.array_equal(s1, oracle.minhash_doc(doubled, 1, a, b))
+
+
+def _disjoint_pair(rng, n_sh, shared, w=5):
+    """Two documents of distinct random tokens whose w-shingle sets share
+    exactly `shared` shingles (a common prefix of shared+w-1 tokens)."""
+    base = rng.choice(2**31, size=2 * (n_sh + w), replace=False).astype(np.uint32) + 1_000_000
+    pre = base[: shared + w - 1] if shared else base[:0]
+    rest_a = base[shared + w - 1: shared + w - 1 + (n_sh - shared)]
+    rest_b = base[n_sh + w: n_sh + w + (n_sh - shared)]
+    A = np.concatenate([pre, rest_a, base[-(w - 1):]]) if shared else base[: n_sh + w - 1]
+    B = np.concatenate([pre, rest_b]) if shared else base[n_sh + w - 1: 2 * n_sh + 2 * w - 2]
+    return A.astype(np.uint32), B.astype(np.uint32)
+
+
+def _jaccard(A, B, w=5):
+    sa = {tuple(A[t:t + w]) for t in range(len(A) - w + 1)}
+    sb = {tuple(B[t:t + w]) for t in range(len(B) - w + 1)}
+    return len(sa & sb) / len(sa | sb)
+
+
+def test_minhash_estimator_binomial_bound():
+    """P[sig_i(A) = sig_i(B)] = J (Section 2.2); over many pairs the estimate
+    stays within 4 binomial standard deviations and is unbiased."""
+    P = 128
+    idx = oracle.OracleIndex(P, 16, 8, 1000, 1e-3, seed=2024)
+    a, b, _ = idx.coeffs()
+    rng = np.random.default_rng(1)
+    errs, zs = [], []
+    for pair in range(300):
+        n_sh = 60
+        shared = int(rng.integers(0, n_sh + 1))
+        A, B = _disjoint_pair(rng, n_sh, shared)
+        J = _jaccard(A, B)
+        sa, sb = oracle.minhash_doc(A, 5, a, b), oracle.minhash_doc(B, 5, a, b)
+        Jh = float(np.mean(sa == sb))
+        errs.append(Jh - J)
+        sd = math.sqrt(max(J * (1 - J), 1e-12) / P)
+        zs.append(abs(Jh - J) / sd if 0 < J < 1 else (0.0 if Jh == J else 99.0))
+    assert np.mean(np.array(zs) <= 4.0) >= 0.99
+    assert abs(np.mean(errs)) < 4 * 0.5 / math.sqrt(P * len(errs))
+
+
+# -------------------------------------------------------------- band key ----
+
+def test_band_key_equal_tuples_equal_keys():
+    idx = oracle.OracleIndex(32, 4, 8, 1000, 1e-3, seed=5)
+    rng = np.random.default_rng(2)
+    s1 = rng.integers(0, 2**32, 32, dtype=np.uint64).astype(np.uint32)
+    s2 = rng.integers(0, 2**32, 32, dtype=np.uint64).astype(np.uint32)
+    s2[8:16] = s1[8:16]
+    k1, k2 = idx.band_keys(s1)[0], idx.band_keys(s2)[0]
+    assert k1[1] == k2[1]
+    assert (k1[[0, 2, 3]] != k2[[0, 2, 3]]).all()
+
+
+def test_band_key_is_a_sum_of_per_row_terms():
+    """h(x) = (sum_i h_i(x_i)) mod N (Section 4.1): swapping one row between two
+    tuples leaves the sum of their keys unchanged mod 2^64."""
+    idx = oracle.OracleIndex(8, 1, 8, 1000, 1e-3, seed=77)
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        x = rng.integers(0, 2**32, 8, dtype=np.uint64).astype(np.uint32)
+        y = rng.integers(0, 2**32, 8, dtype=np.uint64).astype(np.uint32)
+        t = int(rng.integers(0, 8))
+        x2, y2 = x.copy(), y.copy()
+        x2[t], y2[t] = y[t], x[t]
+        kx, ky, kx2, ky2 = (int(idx.band_keys(s)[0, 0]) for s in (x, y, x2, y2))
+        assert (kx + ky) % 2**64 == (kx2 + ky2) % 2**64
+        # the row index enters the summand: moving a value to another row changes the key
+        z = x.copy()
+        z[[0, 1]] = x[[1, 0]]
+        if x[0] != x[1]:
+            assert int(idx.band_keys(z)[0, 0]) != kx
+
+
+def test_band_keys_do_not_collide():
+    idx = oracle.OracleIndex(8, 1, 8, 1000, 1e-3, seed=9)
+    rng = np.random.default_rng(4)
+    sigs = rng.integers(0, 2**32, (400_000, 8), dtype=np.uint64).astype(np.uint32)
+    keys = idx.band_keys(sigs)[:, 0]
+    assert len(np.unique(keys)) == len(np.unique(sigs, axis=0))
+
+
+# ---------------------------------------------------------- Bloom filter ----
+
+def test_positions_in_range_and_spread():
+    m, k = 1_000_003 * 64, 17
+    rng = np.random.default_rng(6)
+    allg = []
+    for _ in range(2000):
+        g = oracle.positions(int(rng.integers(0, 2**63)), 12345, 67890, m, k)
+        assert (g < m).all()
+        allg.append(g)
+    allg = np.concatenate(allg).astype(np.float64) / m
+    # uniform on [0,1): KS-style check on 34,000 positions
+    allg.sort()
+    ecdf = np.arange(1, len(allg) + 1) / len(allg)
+    assert np.max(np.abs(ecdf - allg)) < 1.63 / math.sqrt(len(allg)) * 1.5
+
+
+def test_no_false_negatives():
+    """Section 2.4: a Bloom filter has no false negatives: every inserted key
+    is found, and a repeated document is always flagged."""
+    idx = oracle.OracleIndex(64, 8, 8, 5000, 1e-2, seed=1)
+    rng = np.random.default_rng(10)
+    sigs = rng.integers(0, 2**32, (3000, 64), dtype=np.uint64).astype(np.uint32)
+    idx.insert(sigs)
+    assert idx.query(sigs).all()
+    stream = np.concatenate([sigs[:100], sigs[:100]])
+    idx2 = oracle.OracleIndex(64, 8, 8, 5000, 1e-2, seed=1)
+    f = idx2.query_insert(stream)
+    assert f[100:].all()
+
+
+@pytest.mark.parametrize("bands", [1, 4])
+def test_bloom_false_positive_law(bands):
+    """Fill with n keys, probe fresh ones: FP = (1 - e^{-kn/m})^k per band and
+    1-(1-FP)^b over b bands (Section 4.3)."""
+    n = 20_000
+    idx = oracle.OracleIndex(8 * bands, bands, 8, n, 1e-3, seed=17 + bands)
+    rng = np.random.default_rng(12 + bands)
+    ins = rng.integers(0, 2**32, (n, 8 * bands), dtype=np.uint64).astype(np.uint32)
+    idx.insert(ins)
+    probe = rng.integers(0, 2**32, (200_000, 8 * bands), dtype=np.uint64).astype(np.uint32)
+    got = idx.query(probe).mean()
+    m, k = idx.m_bits, idx.k
+    f = (1 - math.exp(-k * n / m)) ** k
+    want = 1 - (1 - f) ** bands
+    sd = math.sqrt(want * (1 - want) / len(probe))
+    assert abs(got - want) < 4.5 * sd, (got, want)
+    # sized for n at p: the per-band rate is close to the requested 1e-3
+    assert 0.8e-3 < f < 1.25e-3
+
+
+def test_p_eff_composition_over_a_stream():
+    """Unique random documents streamed through query-then-insert: the expected
+    number flagged is sum_i 1-(1-FP_i)^b with FP_i the Bloom rate after i
+    inserts (Section 4.3)."""
+    n, bands = 30_000, 8
+    idx = oracle.OracleIndex(64, bands, 8, n, 5e-3, seed=31)
+    rng = np.random.default_rng(13)
+    sigs = rng.integers(0, 2**32, (n, 64), dtype=np.uint64).astype(np.uint32)
+    got = int(idx.query_insert(sigs).sum())
+    m, k = idx.m_bits, idx.k
+    i = np.arange(n)
+    f = (1 - np.exp(-k * i / m)) ** k
+    want = float(np.sum(1 - (1 - f) ** bands))
+    assert abs(got - want) < 4.5 * math.sqrt(want) + 2, (got, want)
+
+
+# ------------------------------------------------------- sizing (§4.3/4.5) ----
+
+def test_params_match_closed_form():
+    for n, p in [(2000, 1e-5), (10**6, 1e-6), (10**8, 1e-8), (10**9, 1e-10), (7, 0.5)]:
+        m, k = oracle.params(n, p)
+        exact = -n * math.log(p) / math.log(2) ** 2
+        assert m % 64 == 0 and exact <= m < exact + 64
+        assert k == max(1, round(-math.log2(p)))
+
+
+def test_paper_band_choice():
+    for v in _golden("paper_sizing.json")["band_choice"]:
+        b, r = oracle.optimal_br(v["threshold"], v["num_perm"])
+        assert b == v["bands"], v["cite"]
+
+
+def test_paper_index_sizes():
+    for v in _golden("paper_sizing.json")["index_size"]:
+        p = oracle.p_band_from_eff(v["p_eff"], v["bands"])
+        m, _ = oracle.params(int(v["n"]), p)
+        size = v["bands"] * m / 8
+        assert abs(size - v["bytes"]) / v["bytes"] < v["rel_tol"], (v["cite"], size)
+
+
+def test_p_eff_round_trip():
+    for b in [1, 9, 16, 42]:
+        for pe in [1e-3, 1e-5, 1e-10]:
+            p = oracle.p_band_from_eff(pe, b)
+            assert abs(oracle.p_eff_from_band(p, b) - pe) / pe < 1e-6
+            assert abs(p - pe / b) / (pe / b) < 1e-2  # small-p limit p ~ p_eff / b
+
+
+def test_fp_fn_integrals_against_quadrature():
+    from scipy.integrate import quad
+
+    # b = r = 1: closed forms T^2/2 and (1-T)^2/2
+    for T in [0.2, 0.5, 0.8]:
+        assert abs(oracle.fp_lsh(T, 1, 1) - T * T / 2) < 1e-10
+        assert abs(oracle.fn_lsh(T, 1, 1) - (1 - T) ** 2 / 2) < 1e-10
+    for T, b, r in [(0.5, 42, 6), (0.8, 9, 13), (0.3, 16, 8)]:
+        fp = quad(lambda t: 1 - (1 - t ** r) ** b, 0, T)[0]
+        fn = quad(lambda t: (1 - t ** r) ** b, T, 1)[0]
+        assert abs(oracle.fp_lsh(T, b, r) - fp) < 1e-7
+        assert abs(oracle.fn_lsh(T, b, r) - fn) < 1e-7
+
+
+# ------------------------------------------------------------- S-curve ----
+
+@pytest.mark.parametrize("s,lo_hi", [(0.5, None), (0.7, None), (0.8, None)])
+def test_lsh_s_curve(s, lo_hi):
+    """P[some band of two documents matches] = 1-(1-s^r)^b (Section 2.3,
+    Eq. 1-2 integrand) for pairs of exact Jaccard s: insert A, query B."""
+    P, b, r = 128, 16, 8
+    n_pairs = 500
+    n_sh = 57
+    # shared shingles c give J = c / (2 n_sh - c)
+    c = int(round(2 * n_sh * s / (1 + s)))
+    rng = np.random.default_rng(int(s * 100))
+    idx = oracle.OracleIndex(P, b, r, 10 * n_pairs, 1e-9, seed=4242)
+    Js, As, Bs = [], [], []
+    for _ in range(n_pairs):
+        A, B = _disjoint_pair(rng, n_sh, c)
+        As.append(A)
+        Bs.append(B)
+    J = _jaccard(As[0], Bs[0])
+    offs = np.zeros(n_pairs + 1, np.int64)
+    offs[1:] = np.cumsum([len(x) for x in As])
+    sa = idx.minhash(offs, np.concatenate(As))
+    offs[1:] = np.cumsum([len(x) for x in Bs])
+    sb = idx.minhash(offs, np.concatenate(Bs))
+    idx.insert(sa)
+    got = idx.query(sb).mean()
+    want = 1 - (1 - J ** r) ** b
+    sd = math.sqrt(want * (1 - want) / n_pairs)
+    assert abs(got - want) < 4 * sd + 0.01, (J, got, want)
+
+
+# ----------------------------------------- exact MinHashLSH containment ----
+
+def test_exact_lsh_flags_are_contained_in_lshbloom_flags():
+    """A hash set of band tuples (the traditional LSH index of Section 2.3)
+    flags a subset of what the Bloom index flags; the excess is the Bloom
+    false-positive overhead (Section 4.3), small at this fill."""
+    from paper_2411_04257_amd import synth
+
+    wl = synth.WORKLOADS["c1"]
+    corpus = synth.make_corpus(wl, n_docs=800)
+    off = corpus.offsets.numpy()
+    tok = corpus.tokens.numpy().view(np.uint32)
+    idx = oracle.OracleIndex(wl.num_perm, wl.bands, wl.rows, 800, 1e-4, seed=wl.index_seed)
+    sigs = idx.minhash(off, tok)
+    flags = idx.query_insert(sigs)
+    seen = [set() for _ in range(wl.bands)]
+    exact = np.zeros(len(sigs), np.uint8)
+    for i, s in enumerate(sigs):
+        tups = [tuple(s[j * wl.rows:(j + 1) * wl.rows]) for j in range(wl.bands)]
+        exact[i] = any(t in seen[j] for j, t in enumerate(tups))
+        for j, t in enumerate(tups):
+            seen[j].add(t)
+    assert (flags >= exact).all()
+    assert exact.sum() > 20
+    assert (flags.sum() - exact.sum()) <= 5
+
+
+def test_fidelity_on_brute_force_jaccard():
+    """F(d_i) of Section 2.1 computed by brute-force pairwise Jaccard on a
+    tiny corpus: near-certain detection above J = 0.9, near-zero flags below
+    J = 0.3 (b = 16, r = 8 puts the S-curve midpoint near 0.7)."""
+    from paper_2411_04257_amd import synth
+
+    wl = synth.WORKLOADS["c2"]
+    corpus = synth.make_corpus(wl, n_docs=300)
+    off = corpus.offsets.numpy()
+    tok = corpus.tokens.numpy().view(np.uint32)
+    docs = [tok[off[i]:off[i + 1]] for i in range(300)]
+    sets = [{tuple(d[t:t + 5]) for t in range(len(d) - 4)} for d in docs]
+    maxJ = np.zeros(300)
+    for i in range(300):
+        for j in range(i):
+            inter = len(sets[i] & sets[j])
+            if inter:
+                maxJ[i] = max(maxJ[i], inter / len(sets[i] | sets[j]))
+    idx = oracle.OracleIndex(wl.num_perm, wl.bands, wl.rows, 300, 1e-6, seed=wl.index_seed)
+    flags = idx.query_insert(idx.minhash(off, tok))
+    hi = maxJ >= 0.9
+    lo = maxJ < 0.3
+    assert hi.sum() >= 5 and lo.sum() >= 200
+    assert flags[hi].all()
+    assert flags[lo].sum() == 0
+    # in between, the detection rate tracks the S-curve on average
+    mid = (maxJ >= 0.6) & (maxJ < 0.9)
+    if mid.sum() >= 10:
+        want = np.mean(1 - (1 - maxJ[mid] ** 8) ** 16)
+        assert abs(flags[mid].mean() - want) < 0.35
