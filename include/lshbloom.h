@@ -1,0 +1,198 @@
+/*
+ * lshbloom.h — C ABI of the MI355X (gfx950) LSHBloom hot path.
+ *
+ * LSHBloom ("LSHBloom: Internet-Scale Text Deduplication", arXiv 2411.04257)
+ * answers the streaming question of Section 2.1: for each document d_i of a
+ * stream, is some earlier document d_j (j < i) similar to it?  The hot path
+ * has three steps, all run by hand-written HIP kernels behind this ABI:
+ *
+ *   1. MinHash (Section 2.2): a document is the set of its w-token shingles;
+ *      signature row i is min over shingles of h_i(shingle hash).
+ *   2. Band keys (Sections 2.3, 4.1): rows are grouped in b bands of r rows
+ *      and each band is reduced to one 64-bit key by a sum of per-row hashes
+ *      mod N, N = 2^64.
+ *   3. One Bloom filter per band (Sections 2.4, 4, 4.2): a document is flagged
+ *      when, in some band, all k filter bits of its key are already set; then
+ *      its bits are set in every band.  Flags are exactly those of processing
+ *      the documents one at a time in stream order (Section 4.4.2).
+ *
+ * Exact definitions (bit-for-bit; every GPU result equals the sequential
+ * definition below, including the final filter bits):
+ *   - shingles of a document of L tokens: tokens[t..t+w-1] for t = 0..L-w when
+ *     L >= w; one shingle of all L tokens when 1 <= L < w; none when L = 0.
+ *   - shingle hash x: SHA-1 (FIPS 180-4) of the shingle's tokens as
+ *     little-endian uint32 bytes; x = first four digest bytes, little-endian.
+ *   - h_i(x) = ((a_i * x + b_i) mod (2^61 - 1)) mod 2^32, exact; an empty
+ *     document has the all-0xFFFFFFFF signature.
+ *   - coefficients: SplitMix64 stream from `seed` (state += 0x9E3779B97F4A7C15,
+ *     output = the standard SplitMix64 finalizer of the state); a_0..a_{P-1}
+ *     are successive outputs >> 3, redrawn while 0 or >= 2^61-1; then
+ *     b_0..b_{P-1} the same, redrawn while >= 2^61-1; then salt_M, salt_1,
+ *     salt_2 are three raw outputs.
+ *   - band key K_j = sum_{t<r} fmix64((sig[j*r+t] | t << 32) ^ salt_M)
+ *     mod 2^64, where fmix64 is the SplitMix64 finalizer.  Rows from b*r to
+ *     P-1 are not used.
+ *   - positions: h1 = fmix64(K_j ^ salt_1), h2 = fmix64(K_j ^ salt_2) | 1,
+ *     g_l = floor(((h1 + l*h2) mod 2^64) * m / 2^64), l = 0..k-1.
+ *   - filter of band j: m bits in m/64 little-endian uint64 words; bit g is
+ *     bit (g & 63) of word g >> 6.
+ *   - sizing (Section 4.5): m = 64 * ceil((-(n * ln p) / (ln 2 * ln 2)) / 64)
+ *     evaluated in IEEE double in that order, with n = expected_n and
+ *     p = fp_rate, the per-band false-positive rate; k = max(1,
+ *     floor(-log2(p) + 0.5)).  The effective rate over b bands is
+ *     p_eff = 1 - (1 - p)^b (Section 4.3).
+ *
+ * Memory: every pointer argument named d_* is a device pointer in the
+ * caller's ownership (for example a torch CUDA tensor's data_ptr()).  The
+ * library owns its filters and workspace, allocates them once in create and
+ * frees them in destroy; the hot-path calls allocate nothing.
+ *
+ * Streams: every call is asynchronous on `stream` (a hipStream_t; NULL is the
+ * null stream).  Calls that read or change the filters of one handle are
+ * serialised in host call order whatever stream they use: each waits for the
+ * previous one (an event kept in the handle).  Document order is therefore
+ * host call order, then index within a call.  lshbloom_minhash touches no
+ * handle state and may run concurrently on any stream.
+ *
+ * Errors: functions returning int give LSHBLOOM_OK (0) or a negative code;
+ * lshbloom_last_error() returns a message for the calling thread's last
+ * failure.  Invalid arguments are rejected before anything is launched.  A
+ * device error inside a filter-changing call poisons the handle (its filters
+ * may be half-written): every later call on it returns LSHBLOOM_EPOISONED.
+ * Device-side data (offsets, tokens) is trusted: offsets must be
+ * non-decreasing and in bounds of d_tokens.
+ *
+ * Thread safety: one handle may be used from several host threads; calls are
+ * serialised internally.
+ */
+#ifndef LSHBLOOM_H
+#define LSHBLOOM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lshbloom lshbloom_t;
+typedef void *lshbloom_stream_t; /* a hipStream_t */
+
+enum {
+  LSHBLOOM_OK = 0,
+  LSHBLOOM_EINVAL = -1,    /* bad argument; nothing was launched */
+  LSHBLOOM_ENOMEM = -2,    /* device memory (or the HBM budget) exhausted */
+  LSHBLOOM_EHIP = -3,      /* HIP runtime error; message in last_error */
+  LSHBLOOM_EPOISONED = -4, /* an earlier device error left the filters indeterminate */
+};
+
+/* Limits of this implementation. */
+#define LSHBLOOM_MAX_NUM_PERM 512u        /* signature width P */
+#define LSHBLOOM_MAX_BANDS 64u            /* b */
+#define LSHBLOOM_MAX_SHINGLE_WIDTH 13u    /* w: one shingle fits one SHA-1 block */
+#define LSHBLOOM_MAX_M_BITS 0xFFFFFFFFC0ull /* m < 2^40 bits per band */
+
+typedef struct lshbloom_params {
+  uint32_t num_perm;      /* P >= 1, <= LSHBLOOM_MAX_NUM_PERM */
+  uint32_t bands;         /* b >= 1, <= LSHBLOOM_MAX_BANDS */
+  uint32_t rows;          /* r >= 1, b * r <= P */
+  uint64_t expected_n;    /* n >= 1: documents the filters are sized for */
+  double fp_rate;         /* per-band false-positive rate p, 0 < p < 1 */
+  uint64_t seed;          /* coefficient and salt stream seed */
+  uint32_t shingle_width; /* w, 1..LSHBLOOM_MAX_SHINGLE_WIDTH; 0 means 5 */
+  uint64_t hbm_budget;    /* bytes the handle may allocate; 0 = no limit */
+  uint64_t chunk_docs;    /* documents per in-order query-insert chunk; 0 = automatic */
+} lshbloom_params_t;
+
+typedef struct lshbloom_info {
+  uint32_t num_perm, bands, rows, shingle_width;
+  uint32_t k;               /* probes per band */
+  uint64_t m_bits;          /* bits per band */
+  uint64_t words_per_band;  /* m_bits / 64 */
+  uint64_t filter_bytes;    /* bands * m_bits / 8 */
+  uint64_t workspace_bytes; /* device bytes besides the filters */
+  uint64_t chunk_docs;      /* documents per query-insert chunk */
+  double fp_rate;           /* per-band p */
+  double p_eff;             /* 1 - (1 - p)^bands (Section 4.3) */
+  uint64_t docs_inserted;   /* documents inserted so far (host count of calls) */
+  uint64_t seed;
+  int poisoned;
+  uint32_t device_status; /* 0 unless a kernel detected an internal inconsistency */
+} lshbloom_info_t;
+
+/* Create an index of `bands` empty Bloom filters (Section 4: one per band)
+ * sized for expected_n documents at per-band rate fp_rate (Section 4.5), with
+ * shingle width 5.  Allocates the filters and workspace on the current HIP
+ * device.  Returns NULL on error (message in lshbloom_last_error). */
+lshbloom_t *lshbloom_create(uint32_t num_perm, uint32_t bands, uint32_t rows, uint64_t expected_n, double fp_rate,
+                            uint64_t seed);
+
+/* As lshbloom_create, with every parameter of lshbloom_params_t. */
+lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *params);
+
+/* Free the filters and workspace (after synchronising the handle's last
+ * call).  NULL is a no-op. */
+void lshbloom_destroy(lshbloom_t *h);
+
+/* MinHash signatures of a CSR batch (Section 2.2).
+ *   d_offsets: int64 [n_docs + 1], non-decreasing; document d owns
+ *              d_tokens[d_offsets[d] .. d_offsets[d+1]).
+ *   d_tokens:  uint32 token ids.
+ *   d_sigs:    uint32 [n_docs][num_perm] row-major output.
+ * n_docs = 0 is a no-op.  Stateless: runs concurrently with other calls. */
+int lshbloom_minhash(lshbloom_t *h, const int64_t *d_offsets, const uint32_t *d_tokens, int64_t n_docs,
+                     uint32_t *d_sigs, lshbloom_stream_t stream);
+
+/* Query then insert a batch of signatures in stream order (Sections 2.1, 4.1,
+ * 4.2, 4.4.2): d_flags[i] = 1 iff, for some band, all k bits of document i's
+ * key were set by the filters' earlier contents or by documents 0..i-1 of
+ * this batch; then every band's bits of every document are set.
+ *   d_sigs:  uint32 [n_docs][num_perm] (for example lshbloom_minhash output).
+ *   d_flags: uint8 [n_docs] output, 0 or 1.
+ * n_docs = 0 is a no-op. */
+int lshbloom_query_insert(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags,
+                          lshbloom_stream_t stream);
+
+/* Query only (Section 4.2): flags against the filters as they are; nothing is
+ * inserted and documents of the batch do not see each other. */
+int lshbloom_query(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags,
+                   lshbloom_stream_t stream);
+
+/* Insert only (Section 4.1): set every band's bits of every document. */
+int lshbloom_insert(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, lshbloom_stream_t stream);
+
+/* Band keys K_j of each document (Section 4.1), uint64 [n_docs][bands]. */
+int lshbloom_band_keys(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, uint64_t *d_keys,
+                       lshbloom_stream_t stream);
+
+/* Copy nbytes of the filter words, starting at byte `offset` of the
+ * band-major array (band j's words start at byte j * m_bits / 8), to `dst`
+ * (host or device memory), ordered after the handle's previous calls.
+ * Synchronous when dst is pageable host memory. */
+int lshbloom_read_filters(lshbloom_t *h, void *dst, uint64_t offset, uint64_t nbytes, lshbloom_stream_t stream);
+
+/* Overwrite filter bytes from `src` (host or device memory); sets
+ * docs_inserted to `docs_inserted` when it is not UINT64_MAX.  Used to load a
+ * saved index or a preloaded state. */
+int lshbloom_write_filters(lshbloom_t *h, const void *src, uint64_t offset, uint64_t nbytes,
+                           uint64_t docs_inserted, lshbloom_stream_t stream);
+
+/* Parameters, sizes and counters of the handle. */
+int lshbloom_info(const lshbloom_t *h, lshbloom_info_t *out);
+
+/* Per-band rate p that gives an effective rate p_eff over `bands` bands,
+ * p = 1 - (1 - p_eff)^(1/bands) (Section 4.3). */
+double lshbloom_p_band_from_eff(double p_eff, uint32_t bands);
+
+/* (b, r) minimising w_fp * FP_lsh + w_fn * FN_lsh (Section 4.3, Eq. 1-2) over
+ * b * r <= num_perm; returns LSHBLOOM_EINVAL for bad arguments. */
+int lshbloom_optimal_bands(double threshold, uint32_t num_perm, double w_fp, double w_fn, uint32_t *bands,
+                           uint32_t *rows);
+
+/* Message for the calling thread's last failure ("" if none). */
+const char *lshbloom_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSHBLOOM_H */

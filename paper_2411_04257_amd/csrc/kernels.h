@@ -1,0 +1,54 @@
+// Host-side launchers of the LSHBloom HIP kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lb {
+
+// Permutation coefficients as 32-bit halves: {a_lo, a_hi, b_lo, b_hi}.
+struct PermCoef {
+  uint32_t a_lo, a_hi, b_lo, b_hi;
+};
+
+struct MinhashLaunch {
+  const int64_t *offsets;
+  const uint32_t *tokens;
+  int64_t n_docs;
+  const PermCoef *coef;
+  uint32_t *sigs;
+  uint32_t num_perm;
+  uint32_t w;
+  int waves;  // total waves of the persistent grid (multiple of 4)
+};
+
+struct BloomLaunch {
+  const uint32_t *sigs;  // [n][num_perm]
+  int64_t n;
+  uint32_t num_perm, bands, rows, k;
+  uint64_t m_bits, words_per_band;
+  uint64_t salt_m, salt1, salt2;
+  uint64_t *filters;
+  uint64_t *table;  // first-setter table, power-of-two slots
+  uint64_t table_mask;
+  uint64_t *keys;   // [n][bands]
+  uint64_t *masks;  // [n][bands]
+  uint8_t *hitb;    // [n][bands]
+  uint8_t *flags;   // [n]
+  uint32_t *status;  // device status word (nonzero = internal inconsistency)
+};
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
+hipError_t launch_minhash(const MinhashLaunch &a, hipStream_t s);
+hipError_t launch_band_keys(const BloomLaunch &a, hipStream_t s);
+// One in-order chunk: clear table, probe, resolve + insert, flags.
+hipError_t launch_query_insert_chunk(const BloomLaunch &a, uint64_t table_slots, hipStream_t s);
+hipError_t launch_query(const BloomLaunch &a, hipStream_t s);
+hipError_t launch_insert(const BloomLaunch &a, hipStream_t s);
+
+constexpr uint64_t kTableEmpty = ~0ull;
+constexpr int kIdxBits = 18;  // doc index within a chunk
+constexpr uint64_t kMaxChunkDocs = (1ull << kIdxBits) - 1;
+
+}  // namespace lb

@@ -1,0 +1,401 @@
+// LSHBloom hot-path kernels for gfx950 (wave64, VALU integer work, no MFMA).
+//
+//  k_minhash   : Section 2.2.  Persistent grid; each wave owns one contiguous
+//                range of token positions of the whole CSR batch.  Per tile of
+//                64 positions, lane l hashes the shingle starting at position
+//                tile+l (SHA-1), then the wave walks the tile's valid shingles
+//                with lanes = permutations, keeping running minima in VGPRs
+//                across tiles while the document continues.  A document that
+//                lies wholly in the wave's range is stored with plain
+//                coalesced stores; one cut by a range boundary is merged with
+//                atomicMin into a row pre-filled with 0xFFFFFFFF.
+//  k_band_keys : Section 4.1 band keys (export for checking).
+//  k_qi_probe  : Sections 2.4, 4.2.  One thread per (document, band) of a
+//                chunk: band key, k positions, read the filter words; bits
+//                already set are recorded in a mask, bits still clear are
+//                registered in a first-setter table keyed by (band, bit)
+//                whose value is the smallest document index probing it.
+//  k_qi_resolve: the bit was set before document i iff it was set before the
+//                chunk or its first setter is < i (Section 2.1 order); the
+//                band hits iff all k bits were; the first setter of a clear bit
+//                sets it with atomicOr (Section 4.1 insert).
+//  k_qi_flags  : OR over bands (Section 4.2).
+#include <hip/hip_runtime.h>
+
+#include "device_math.h"
+#include "kernels.h"
+
+namespace lb {
+
+namespace {
+
+constexpr int kBlock = 256;
+
+__global__ void k_fill_u32(uint32_t *__restrict__ p, uint64_t n, uint32_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t *__restrict__ p, uint64_t n, uint64_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+// First index i in [0, n) with a[i] > v, or n.
+__device__ __forceinline__ int64_t upper_bound_i64(const int64_t *__restrict__ a, int64_t n, int64_t v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (a[mid] <= v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+__device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
+  const uint32_t lo = (uint32_t)(uint64_t)v, hi = (uint32_t)((uint64_t)v >> 32);
+  const uint32_t rlo = (uint32_t)__shfl((int)lo, src, 64);
+  const uint32_t rhi = (uint32_t)__shfl((int)hi, src, 64);
+  return (int64_t)(((uint64_t)rhi << 32) | rlo);
+}
+
+template <int PPL, int WFIX>
+__global__ __launch_bounds__(kBlock) void k_minhash(MinhashLaunch A) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  const int64_t n_docs = A.n_docs;
+  const int64_t base = A.offsets[0];
+  const int64_t end = A.offsets[n_docs];
+  const int64_t total = end - base;
+  if (total <= 0) return;
+  const int64_t r0 = base + (total * wave) / A.waves;
+  const int64_t r1 = base + (total * (wave + 1)) / A.waves;
+  if (r0 >= r1) return;
+
+  const uint32_t P = A.num_perm;
+  const int64_t w = WFIX ? WFIX : (int64_t)A.w;
+  uint32_t al[PPL], ah[PPL], bl[PPL], bh[PPL], mn[PPL];
+#pragma unroll
+  for (int p = 0; p < PPL; ++p) {
+    const uint32_t i = (uint32_t)p * 64u + (uint32_t)lane;
+    PermCoef c = {0, 0, 0, 0};
+    if (i < P) c = A.coef[i];
+    al[p] = c.a_lo;
+    ah[p] = c.a_hi;
+    bl[p] = c.b_lo;
+    bh[p] = c.b_hi;
+    mn[p] = 0xFFFFFFFFu;
+  }
+
+  // Document containing the first position of the current tile.
+  int64_t dcur = upper_bound_i64(A.offsets, n_docs + 1, r0) - 1;
+  int64_t cur = -1;  // document whose partial minima are held in mn[]
+
+  auto flush = [&](int64_t d) {
+    const int64_t s0 = A.offsets[d], e0 = A.offsets[d + 1];
+    const int64_t last = (e0 - s0 >= w) ? e0 - w : s0;
+    const bool inside = s0 >= r0 && last < r1;
+    uint32_t *row = A.sigs + d * (int64_t)P;
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) {
+      const uint32_t i = (uint32_t)p * 64u + (uint32_t)lane;
+      if (i < P) {
+        if (inside)
+          row[i] = mn[p];
+        else
+          atomicMin(&row[i], mn[p]);
+      }
+      mn[p] = 0xFFFFFFFFu;
+    }
+  };
+
+  for (int64_t tb = r0; tb < r1; tb += 64) {
+    const int64_t pos = tb + lane;
+    const bool in_range = pos < r1;
+    // Ends of documents dcur, dcur+1, ..., dcur+63.
+    const int64_t jd = dcur + 1 + lane;
+    const int64_t e = (jd <= n_docs) ? A.offsets[jd] : INT64_MAX;
+    const int64_t e63 = shfl64(e, 63);
+    int64_t doc, ds, de, dnext;
+    if (e63 > tb + 64) {
+      // The 64-document window covers the tile: count the ends <= pos.
+      int lo = 0;
+#pragma unroll
+      for (int step = 32; step >= 1; step >>= 1) {
+        const int64_t v = shfl64(e, lo + step - 1);
+        if (v <= pos) lo += step;
+      }
+      doc = dcur + lo;
+      de = shfl64(e, lo);
+      const int64_t prev = shfl64(e, lo > 0 ? lo - 1 : 0);
+      ds = lo > 0 ? prev : A.offsets[dcur];
+      dnext = dcur + __popcll(__ballot(e <= tb + 64));
+    } else {
+      // More than 63 documents end inside the tile (empty documents):
+      // search the whole offsets array.
+      doc = upper_bound_i64(A.offsets, n_docs + 1, pos) - 1;
+      if (doc > n_docs - 1) doc = n_docs - 1;
+      ds = A.offsets[doc];
+      de = A.offsets[doc + 1];
+      dnext = upper_bound_i64(A.offsets, n_docs + 1, tb + 64) - 1;
+      if (dnext > n_docs) dnext = n_docs;
+    }
+    const int64_t L = de - ds;
+    const bool valid = in_range && pos >= ds && pos < de && L > 0 && ((L >= w) ? (pos <= de - w) : (pos == ds));
+    uint32_t x = 0;
+    if (valid) {
+      const uint32_t *tp = A.tokens + pos;
+      if (WFIX && L >= w)
+        x = shingle_hash_fixed<(WFIX ? WFIX : 1)>(tp);
+      else
+        x = shingle_hash_var(tp, (uint32_t)(L >= w ? w : L));
+    }
+    const int32_t drel = (int32_t)(doc - dcur);
+
+    uint64_t vm = __ballot(valid);
+    while (vm) {
+      const int s = __ffsll((unsigned long long)vm) - 1;
+      const int32_t dr = __builtin_amdgcn_readlane(drel, s);
+      const int64_t d = dcur + dr;
+      if (d != cur) {
+        if (cur >= 0) flush(cur);
+        cur = d;
+      }
+      const uint64_t seg = __ballot(valid && drel == dr);
+      vm &= ~seg;
+      uint64_t sm = seg;
+      while (sm) {
+        const int s2 = __ffsll((unsigned long long)sm) - 1;
+        sm &= sm - 1;
+        const uint32_t xs = __builtin_amdgcn_readlane(x, s2);
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], perm_lo32(xs, al[p], ah[p], bl[p], bh[p]));
+      }
+    }
+    dcur = dnext;
+  }
+  if (cur >= 0) flush(cur);
+}
+
+__device__ __forceinline__ uint64_t table_slot(uint64_t key, uint64_t mask) {
+  return fmix64(key * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull) & mask;
+}
+
+__global__ __launch_bounds__(kBlock) void k_band_keys(BloomLaunch A) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= A.n * (int64_t)A.bands) return;
+  const int64_t i = t / A.bands;
+  const uint32_t j = (uint32_t)(t - i * A.bands);
+  A.keys[t] = band_key(A.sigs + i * (int64_t)A.num_perm + (int64_t)j * A.rows, A.rows, A.salt_m);
+}
+
+constexpr int kProbeBatch = 8;
+
+__global__ __launch_bounds__(kBlock) void k_qi_probe(BloomLaunch A) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= A.n * (int64_t)A.bands) return;
+  const int64_t i = t / A.bands;
+  const uint32_t j = (uint32_t)(t - i * A.bands);
+  const uint64_t K = band_key(A.sigs + i * (int64_t)A.num_perm + (int64_t)j * A.rows, A.rows, A.salt_m);
+  A.keys[t] = K;
+  const uint64_t h1 = fmix64(K ^ A.salt1);
+  const uint64_t h2 = fmix64(K ^ A.salt2) | 1ull;
+  const uint64_t *F = A.filters + (uint64_t)j * A.words_per_band;
+  uint64_t mask = 0;
+  for (uint32_t l0 = 0; l0 < A.k; l0 += kProbeBatch) {
+    uint64_t g[kProbeBatch], word[kProbeBatch];
+#pragma unroll
+    for (int u = 0; u < kProbeBatch; ++u) {
+      const uint32_t l = l0 + u;
+      g[u] = umulhi64(h1 + (uint64_t)l * h2, A.m_bits);
+      word[u] = (l < A.k) ? F[g[u] >> 6] : ~0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kProbeBatch; ++u) {
+      const uint32_t l = l0 + u;
+      if (l >= A.k) break;
+      if ((word[u] >> (g[u] & 63)) & 1ull) {
+        mask |= 1ull << l;
+      } else {
+        const uint64_t key = ((uint64_t)j << 40) | g[u];
+        const uint64_t ent = (key << kIdxBits) | (uint64_t)i;
+        uint64_t s = table_slot(key, A.table_mask);
+        for (uint64_t tries = 0; tries <= A.table_mask; ++tries) {
+          const uint64_t old = atomicCAS((unsigned long long *)&A.table[s], (unsigned long long)kTableEmpty,
+                                         (unsigned long long)ent);
+          if (old == kTableEmpty) break;
+          if ((old >> kIdxBits) == key) {
+            if ((old & kMaxChunkDocs) > (uint64_t)i) atomicMin((unsigned long long *)&A.table[s], (unsigned long long)ent);
+            break;
+          }
+          s = (s + 1) & A.table_mask;
+        }
+      }
+    }
+  }
+  A.masks[t] = mask;
+}
+
+__global__ __launch_bounds__(kBlock) void k_qi_resolve(BloomLaunch A) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= A.n * (int64_t)A.bands) return;
+  const int64_t i = t / A.bands;
+  const uint32_t j = (uint32_t)(t - i * A.bands);
+  const uint64_t K = A.keys[t];
+  const uint64_t mask = A.masks[t];
+  const uint64_t h1 = fmix64(K ^ A.salt1);
+  const uint64_t h2 = fmix64(K ^ A.salt2) | 1ull;
+  uint64_t *F = A.filters + (uint64_t)j * A.words_per_band;
+  bool hit = true;
+  for (uint32_t l = 0; l < A.k; ++l) {
+    if ((mask >> l) & 1ull) continue;
+    const uint64_t g = umulhi64(h1 + (uint64_t)l * h2, A.m_bits);
+    const uint64_t key = ((uint64_t)j << 40) | g;
+    uint64_t s = table_slot(key, A.table_mask);
+    uint64_t ent = kTableEmpty;
+    for (uint64_t tries = 0; tries <= A.table_mask; ++tries) {
+      ent = A.table[s];
+      if (ent == kTableEmpty || (ent >> kIdxBits) == key) break;
+      s = (s + 1) & A.table_mask;
+    }
+    if (ent == kTableEmpty || (ent >> kIdxBits) != key) {
+      atomicOr(A.status, 1u);  // every clear bit was registered by k_qi_probe
+      hit = false;
+      continue;
+    }
+    const uint64_t fs = ent & kMaxChunkDocs;
+    if (fs >= (uint64_t)i) hit = false;
+    if (fs == (uint64_t)i) atomicOr((unsigned long long *)&F[g >> 6], (unsigned long long)(1ull << (g & 63)));
+  }
+  A.hitb[t] = hit ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_qi_flags(BloomLaunch A) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= A.n) return;
+  const uint8_t *hb = A.hitb + i * (int64_t)A.bands;
+  uint8_t f = 0;
+  for (uint32_t j = 0; j < A.bands; ++j) f |= hb[j];
+  A.flags[i] = f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_query(BloomLaunch A) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= A.n * (int64_t)A.bands) return;
+  const int64_t i = t / A.bands;
+  const uint32_t j = (uint32_t)(t - i * A.bands);
+  const uint64_t K = band_key(A.sigs + i * (int64_t)A.num_perm + (int64_t)j * A.rows, A.rows, A.salt_m);
+  const uint64_t h1 = fmix64(K ^ A.salt1);
+  const uint64_t h2 = fmix64(K ^ A.salt2) | 1ull;
+  const uint64_t *F = A.filters + (uint64_t)j * A.words_per_band;
+  bool hit = true;
+  for (uint32_t l = 0; l < A.k && hit; ++l) {
+    const uint64_t g = umulhi64(h1 + (uint64_t)l * h2, A.m_bits);
+    if (!((F[g >> 6] >> (g & 63)) & 1ull)) hit = false;
+  }
+  A.hitb[t] = hit ? 1 : 0;
+}
+
+__global__ __launch_bounds__(kBlock) void k_insert(BloomLaunch A) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= A.n * (int64_t)A.bands) return;
+  const int64_t i = t / A.bands;
+  const uint32_t j = (uint32_t)(t - i * A.bands);
+  const uint64_t K = band_key(A.sigs + i * (int64_t)A.num_perm + (int64_t)j * A.rows, A.rows, A.salt_m);
+  const uint64_t h1 = fmix64(K ^ A.salt1);
+  const uint64_t h2 = fmix64(K ^ A.salt2) | 1ull;
+  uint64_t *F = A.filters + (uint64_t)j * A.words_per_band;
+  for (uint32_t l = 0; l < A.k; ++l) {
+    const uint64_t g = umulhi64(h1 + (uint64_t)l * h2, A.m_bits);
+    atomicOr((unsigned long long *)&F[g >> 6], (unsigned long long)(1ull << (g & 63)));
+  }
+}
+
+inline unsigned grid_for(uint64_t n) {
+  uint64_t g = (n + kBlock - 1) / kBlock;
+  return (unsigned)(g == 0 ? 1 : g);
+}
+
+inline unsigned fill_grid(uint64_t n) {
+  uint64_t g = (n + kBlock - 1) / kBlock;
+  if (g > 8192) g = 8192;
+  return (unsigned)(g == 0 ? 1 : g);
+}
+
+}  // namespace
+
+hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(fill_grid(n)), dim3(kBlock), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(kBlock), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_minhash(const MinhashLaunch &a, hipStream_t s) {
+  const unsigned blocks = (unsigned)(a.waves / (kBlock / 64));
+  const int ppl = (int)((a.num_perm + 63) / 64);
+  const bool w5 = a.w == 5;
+#define LB_MH(PPL_)                                                                        \
+  do {                                                                                     \
+    if (w5)                                                                                \
+      hipLaunchKernelGGL((k_minhash<PPL_, 5>), dim3(blocks), dim3(kBlock), 0, s, a);       \
+    else                                                                                   \
+      hipLaunchKernelGGL((k_minhash<PPL_, 0>), dim3(blocks), dim3(kBlock), 0, s, a);       \
+  } while (0)
+  if (ppl <= 1)
+    LB_MH(1);
+  else if (ppl <= 2)
+    LB_MH(2);
+  else if (ppl <= 4)
+    LB_MH(4);
+  else
+    LB_MH(8);
+#undef LB_MH
+  return hipGetLastError();
+}
+
+hipError_t launch_band_keys(const BloomLaunch &a, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.n * a.bands;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_band_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_query_insert_chunk(const BloomLaunch &a, uint64_t table_slots, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.n * a.bands;
+  if (n == 0) return hipSuccess;
+  hipError_t e = launch_fill_u64(a.table, table_slots, kTableEmpty, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_qi_probe, dim3(grid_for(n)), dim3(kBlock), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_qi_resolve, dim3(grid_for(n)), dim3(kBlock), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_qi_flags, dim3(grid_for((uint64_t)a.n)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_query(const BloomLaunch &a, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.n * a.bands;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_query, dim3(grid_for(n)), dim3(kBlock), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_qi_flags, dim3(grid_for((uint64_t)a.n)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_insert(const BloomLaunch &a, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.n * a.bands;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_insert, dim3(grid_for(n)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace lb

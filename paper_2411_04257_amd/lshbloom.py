@@ -1,0 +1,252 @@
+"""Python binding of liblshbloom.so (argument marshalling only).
+
+Every method maps onto one C-ABI entry point of include/lshbloom.h; all
+per-document work runs in the library's HIP kernels.  Tensors are torch CUDA
+tensors (PyTorch provides device memory and streams); each call is enqueued on
+torch's current stream.  If the library is not built or cannot be loaded the
+binding raises: there is no fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblshbloom.so")
+
+OK, EINVAL, ENOMEM, EHIP, EPOISONED = 0, -1, -2, -3, -4
+_CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EPOISONED: "EPOISONED"}
+
+
+class LSHBloomError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_CODES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("num_perm", ctypes.c_uint32),
+        ("bands", ctypes.c_uint32),
+        ("rows", ctypes.c_uint32),
+        ("expected_n", ctypes.c_uint64),
+        ("fp_rate", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("shingle_width", ctypes.c_uint32),
+        ("hbm_budget", ctypes.c_uint64),
+        ("chunk_docs", ctypes.c_uint64),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("num_perm", ctypes.c_uint32),
+        ("bands", ctypes.c_uint32),
+        ("rows", ctypes.c_uint32),
+        ("shingle_width", ctypes.c_uint32),
+        ("k", ctypes.c_uint32),
+        ("m_bits", ctypes.c_uint64),
+        ("words_per_band", ctypes.c_uint64),
+        ("filter_bytes", ctypes.c_uint64),
+        ("workspace_bytes", ctypes.c_uint64),
+        ("chunk_docs", ctypes.c_uint64),
+        ("fp_rate", ctypes.c_double),
+        ("p_eff", ctypes.c_double),
+        ("docs_inserted", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64),
+        ("poisoned", ctypes.c_int),
+        ("device_status", ctypes.c_uint32),
+    ]
+
+
+# Every symbol the header declares.
+EXPORTS = [
+    "lshbloom_create", "lshbloom_create_ex", "lshbloom_destroy", "lshbloom_minhash", "lshbloom_query_insert",
+    "lshbloom_query", "lshbloom_insert", "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters",
+    "lshbloom_info", "lshbloom_p_band_from_eff", "lshbloom_optimal_bands", "lshbloom_last_error",
+]
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load liblshbloom.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first (__graft_entry__.build())")
+    L = ctypes.CDLL(path)
+    vp, i64, u32, u64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint64
+    L.lshbloom_create.argtypes = [u32, u32, u32, u64, ctypes.c_double, u64]
+    L.lshbloom_create.restype = vp
+    L.lshbloom_create_ex.argtypes = [ctypes.POINTER(Params)]
+    L.lshbloom_create_ex.restype = vp
+    L.lshbloom_destroy.argtypes = [vp]
+    L.lshbloom_destroy.restype = None
+    L.lshbloom_minhash.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.lshbloom_query_insert.argtypes = [vp, vp, i64, vp, vp]
+    L.lshbloom_query.argtypes = [vp, vp, i64, vp, vp]
+    L.lshbloom_insert.argtypes = [vp, vp, i64, vp]
+    L.lshbloom_band_keys.argtypes = [vp, vp, i64, vp, vp]
+    L.lshbloom_read_filters.argtypes = [vp, vp, u64, u64, vp]
+    L.lshbloom_write_filters.argtypes = [vp, vp, u64, u64, u64, vp]
+    L.lshbloom_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.lshbloom_p_band_from_eff.argtypes = [ctypes.c_double, u32]
+    L.lshbloom_p_band_from_eff.restype = ctypes.c_double
+    L.lshbloom_optimal_bands.argtypes = [ctypes.c_double, u32, ctypes.c_double, ctypes.c_double,
+                                         ctypes.POINTER(u32), ctypes.POINTER(u32)]
+    L.lshbloom_last_error.argtypes = []
+    L.lshbloom_last_error.restype = ctypes.c_char_p
+    for name in ("lshbloom_minhash", "lshbloom_query_insert", "lshbloom_query", "lshbloom_insert",
+                 "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters", "lshbloom_info",
+                 "lshbloom_optimal_bands"):
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return load().lshbloom_last_error().decode()
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise LSHBloomError(rc, last_error())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor, dtypes, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA tensor")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+_U32 = (torch.int32, torch.uint32)
+
+
+def p_band_from_eff(p_eff: float, bands: int) -> float:
+    return float(load().lshbloom_p_band_from_eff(p_eff, bands))
+
+
+def optimal_bands(threshold: float, num_perm: int, w_fp: float = 0.5, w_fn: float = 0.5) -> tuple[int, int]:
+    b, r = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(load().lshbloom_optimal_bands(threshold, num_perm, w_fp, w_fn, ctypes.byref(b), ctypes.byref(r)))
+    return int(b.value), int(r.value)
+
+
+class LSHBloom:
+    """An LSHBloom index on the current GPU: one Bloom filter per band."""
+
+    def __init__(self, num_perm: int, bands: int, rows: int, expected_n: int, fp_rate: float, seed: int = 42,
+                 shingle_width: int = 5, hbm_budget: int = 0, chunk_docs: int = 0):
+        L = load()
+        p = Params(num_perm, bands, rows, int(expected_n), float(fp_rate), int(seed), shingle_width,
+                   int(hbm_budget), int(chunk_docs))
+        self._h = L.lshbloom_create_ex(ctypes.byref(p))
+        if not self._h:
+            raise LSHBloomError(EINVAL, last_error())
+        self.num_perm, self.bands, self.rows = num_perm, bands, rows
+        inf = self.info()
+        self.k, self.m_bits, self.words_per_band = inf["k"], inf["m_bits"], inf["words_per_band"]
+
+    # -- lifecycle -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            load().lshbloom_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- hot path ------------------------------------------------------------
+    def minhash(self, offsets: torch.Tensor, tokens: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        n = offsets.numel() - 1
+        if out is None:
+            out = torch.empty((max(n, 0), self.num_perm), dtype=torch.int32, device=offsets.device)
+        if n <= 0:
+            return out
+        if out.shape != (n, self.num_perm):
+            raise ValueError("out must have shape [n_docs, num_perm]")
+        _check(load().lshbloom_minhash(self._h, _dev_ptr(offsets, (torch.int64,), "offsets"),
+                                       _dev_ptr(tokens, _U32, "tokens") if tokens.numel() else ctypes.c_void_p(
+                                           offsets.data_ptr()),
+                                       n, _dev_ptr(out, _U32, "out"), _stream()))
+        return out
+
+    def query_insert(self, sigs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        n = self._rows_of(sigs)
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=sigs.device)
+        if n:
+            _check(load().lshbloom_query_insert(self._h, _dev_ptr(sigs, _U32, "sigs"), n,
+                                                _dev_ptr(out, (torch.uint8,), "out"), _stream()))
+        return out
+
+    def query(self, sigs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        n = self._rows_of(sigs)
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=sigs.device)
+        if n:
+            _check(load().lshbloom_query(self._h, _dev_ptr(sigs, _U32, "sigs"), n,
+                                         _dev_ptr(out, (torch.uint8,), "out"), _stream()))
+        return out
+
+    def insert(self, sigs: torch.Tensor) -> None:
+        n = self._rows_of(sigs)
+        if n:
+            _check(load().lshbloom_insert(self._h, _dev_ptr(sigs, _U32, "sigs"), n, _stream()))
+
+    def band_keys(self, sigs: torch.Tensor) -> torch.Tensor:
+        n = self._rows_of(sigs)
+        out = torch.empty((n, self.bands), dtype=torch.int64, device=sigs.device)
+        if n:
+            _check(load().lshbloom_band_keys(self._h, _dev_ptr(sigs, _U32, "sigs"), n,
+                                             _dev_ptr(out, (torch.int64,), "out"), _stream()))
+        return out
+
+    # -- filters -------------------------------------------------------------
+    def read_filters(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Filter words as int64 [bands, words_per_band] (uint64 bit patterns)."""
+        if out is None:
+            out = torch.empty((self.bands, self.words_per_band), dtype=torch.int64, device="cuda")
+        nbytes = out.numel() * 8
+        ptr = out.data_ptr()
+        _check(load().lshbloom_read_filters(self._h, ctypes.c_void_p(ptr), 0, nbytes, _stream()))
+        return out
+
+    def write_filters(self, words: torch.Tensor, docs_inserted: int | None = None) -> None:
+        if not words.is_contiguous():
+            raise ValueError("words must be contiguous")
+        di = (1 << 64) - 1 if docs_inserted is None else int(docs_inserted)
+        _check(load().lshbloom_write_filters(self._h, ctypes.c_void_p(words.data_ptr()), 0, words.numel() * 8, di,
+                                             _stream()))
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(load().lshbloom_info(self._h, ctypes.byref(inf)))
+        return {name: getattr(inf, name) for name, _ in Info._fields_}
+
+    def _rows_of(self, sigs: torch.Tensor) -> int:
+        if sigs.dim() != 2 or sigs.shape[1] != self.num_perm:
+            raise ValueError(f"signatures must have shape [n, {self.num_perm}]")
+        return int(sigs.shape[0])

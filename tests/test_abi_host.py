@@ -1,0 +1,169 @@
+"""CPU-side checks of the C-ABI library and of its integer building blocks.
+
+No GPU is needed: the library must load and export every declared symbol,
+reject bad parameters before touching the device, and its host-side helpers
+(sizing conversions, band tuning) must agree with the paper's numbers.  The
+device arithmetic header is compiled for the host and checked against big
+integers and hashlib.
+"""
+
+import ctypes
+import hashlib
+import json
+import math
+import os
+import re
+import struct
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lshbloom.h")
+P61 = (1 << 61) - 1
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2411_04257_amd import lshbloom
+
+    return lshbloom.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    src = open(HEADER).read()
+    names = set(re.findall(r"\b(lshbloom_[a-z_]+)\s*\(", src))
+    assert len(names) >= 14
+    from paper_2411_04257_amd import lshbloom
+
+    assert names == set(lshbloom.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_bad_parameters_rejected_without_device(lib):
+    from paper_2411_04257_amd import lshbloom
+
+    for args, needle in [((128, 17, 8, 1000, 1e-3, 1), "bands * rows"), ((0, 1, 1, 1000, 1e-3, 1), "num_perm"),
+                         ((128, 16, 8, 0, 1e-3, 1), "expected_n"), ((128, 16, 8, 1000, 0.0, 1), "fp_rate"),
+                         ((128, 65, 1, 1000, 1e-3, 1), "bands"), ((128, 16, 8, 10**15, 1e-10, 1), "limit")]:
+        assert lib.lshbloom_create(*args) is None
+        assert needle in lshbloom.last_error()
+    p = lshbloom.Params(128, 16, 8, 1000, 1e-3, 1, 14, 0, 0)
+    assert lib.lshbloom_create_ex(ctypes.byref(p)) is None
+    assert "shingle_width" in lshbloom.last_error()
+    p = lshbloom.Params(128, 16, 8, 10**6, 1e-6, 1, 5, 1 << 20, 0)
+    assert lib.lshbloom_create_ex(ctypes.byref(p)) is None
+    assert "budget" in lshbloom.last_error()
+
+
+def test_null_handle_calls_fail_cleanly(lib):
+    assert lib.lshbloom_query_insert(None, None, 0, None, None) == -1
+    assert lib.lshbloom_minhash(None, None, None, 0, None, None) == -1
+    lib.lshbloom_destroy(None)
+
+
+def test_p_band_from_eff_matches_section_4_3():
+    from paper_2411_04257_amd import lshbloom
+
+    for b in [1, 9, 16, 42]:
+        for pe in [1e-3, 1e-5, 1e-10]:
+            p = lshbloom.p_band_from_eff(pe, b)
+            # (1 - p)^b evaluated without cancellation
+            assert abs(-math.expm1(b * math.log1p(-p)) - pe) / pe < 1e-9
+
+
+def test_optimal_bands_reproduce_the_paper():
+    from paper_2411_04257_amd import lshbloom
+
+    golden = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_sizing.json")))
+    for v in golden["band_choice"]:
+        b, r = lshbloom.optimal_bands(v["threshold"], v["num_perm"])
+        assert b == v["bands"], v["cite"]
+
+
+def test_optimal_bands_agree_with_oracle():
+    import oracle
+    from paper_2411_04257_amd import lshbloom
+
+    for T, P in [(0.3, 64), (0.5, 128), (0.7, 100), (0.9, 32)]:
+        assert lshbloom.optimal_bands(T, P) == oracle.optimal_br(T, P)
+
+
+# ------------------------------------------- device arithmetic on the host ----
+
+_HARNESS = r"""
+#include "device_math.h"
+extern "C" {
+uint32_t h_perm(uint32_t x, uint64_t a, uint64_t b) {
+  return lb::perm_lo32(x, (uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+}
+uint32_t h_shingle5(const uint32_t* t) { return lb::shingle_hash_fixed<5>(t); }
+uint32_t h_shingle(const uint32_t* t, uint32_t n) { return lb::shingle_hash_var(t, n); }
+uint64_t h_band_key(const uint32_t* row, uint32_t r, uint64_t salt) { return lb::band_key(row, r, salt); }
+uint64_t h_mulhi(uint64_t a, uint64_t b) { return lb::umulhi64(a, b); }
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("dm")
+    src = d / "h.cpp"
+    src.write_text(_HARNESS)
+    so = d / "h.so"
+    subprocess.check_call(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-I",
+                           os.path.join(ROOT, "paper_2411_04257_amd", "csrc"), str(src), "-o", str(so)])
+    L = ctypes.CDLL(str(so))
+    L.h_perm.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64]
+    L.h_perm.restype = ctypes.c_uint32
+    L.h_shingle5.argtypes = [ctypes.c_void_p]
+    L.h_shingle5.restype = ctypes.c_uint32
+    L.h_shingle.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
+    L.h_shingle.restype = ctypes.c_uint32
+    L.h_band_key.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64]
+    L.h_band_key.restype = ctypes.c_uint64
+    L.h_mulhi.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+    L.h_mulhi.restype = ctypes.c_uint64
+    return L
+
+
+def test_device_perm_matches_big_integers(harness):
+    rng = np.random.default_rng(0)
+    cases = [(0, 1, 0), (2**32 - 1, P61 - 1, P61 - 1), (2**32 - 1, P61 - 1, 0), (1, P61 - 1, 1),
+             (2**32 - 1, 2**32 - 1, P61 - 1), (2**31, (1 << 60) + 1, (1 << 60) - 1)]
+    # values where a*x+b lands on or just above multiples of p
+    for q in range(1, 50):
+        x = int(rng.integers(1, 2**32))
+        a = int(rng.integers(1, P61))
+        b = (q * P61 - (a * x) % P61) % P61
+        cases += [(x, a, b), (x, a, (b + 1) % P61), (x, a, (b - 1) % P61)]
+    for _ in range(100_000):
+        cases.append((int(rng.integers(0, 2**32)), int(rng.integers(1, P61)), int(rng.integers(0, P61))))
+    for x, a, b in cases:
+        assert harness.h_perm(x, a, b) == ((a * x + b) % P61) & 0xFFFFFFFF, (x, a, b)
+
+
+def test_device_shingle_hash_matches_hashlib(harness):
+    rng = np.random.default_rng(1)
+    for n in range(1, 14):
+        for _ in range(200):
+            t = rng.integers(0, 2**32, n, dtype=np.uint64).astype(np.uint32)
+            want = struct.unpack("<I", hashlib.sha1(t.astype("<u4").tobytes()).digest()[:4])[0]
+            assert harness.h_shingle(t.ctypes.data, n) == want
+            if n == 5:
+                assert harness.h_shingle5(t.ctypes.data) == want
+
+
+def test_device_band_key_and_mulhi(harness):
+    import oracle
+
+    rng = np.random.default_rng(2)
+    for _ in range(2000):
+        r = int(rng.integers(1, 17))
+        row = rng.integers(0, 2**32, r, dtype=np.uint64).astype(np.uint32)
+        salt = int(rng.integers(0, 2**63))
+        assert harness.h_band_key(row.ctypes.data, r, salt) == oracle.band_key(row, 0, r, salt)
+        a, b = int(rng.integers(0, 2**64, dtype=np.uint64)), int(rng.integers(0, 2**64, dtype=np.uint64))
+        assert harness.h_mulhi(a, b) == (a * b) >> 64
