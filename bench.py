@@ -27,11 +27,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # Per-unit VALU lane-operation counts of the MinHash hot loops (gfx950 ISA of
-# k_minhash<PPL=2, w=5>): one SHA-1 shingle hash of a 5-token shingle, and one
-# exact (a*x+b) mod (2^61-1) evaluation plus its running min.
-OPS_PER_SHINGLE_HASH = 685
-OPS_PER_SHINGLE_PERM = 10.5
+# k_minhash<PPL=2, w=5>): one SHA-1 shingle hash of a 5-token shingle (573),
+# and one exact (a*x+b) mod (2^61-1) evaluation with its share of the running
+# min (8 + 1/2 of a v_min3 shared by two shingles).
+OPS_PER_SHINGLE_HASH = 573
+OPS_PER_SHINGLE_PERM = 8.5
 INT32_VALU_PEAK = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
+# HBM bytes per token that k_minhash moved, from rocprofv3 FETCH_SIZE (x2.0) and
+# WRITE_SIZE (x1.0) scaled by a 1 GiB copy (profiles/k_minhash_c2_counters.md):
+# 1.126e9 B for a 2.72e8-token batch.  Valid for the kernel version profiled.
+MINHASH_HBM_BYTES_PER_TOKEN = 1.126e9 / 2.7207e8
 
 
 def parse():
@@ -42,6 +47,9 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=["c2"])
     ap.add_argument("--cpu-sample-docs", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-bytes", type=int, default=0,
+                    help="after the timed steps, one device-to-device copy of this many bytes "
+                         "(calibrates the HBM byte counters against a plain copy)")
     return ap.parse_args()
 
 
@@ -167,12 +175,18 @@ def main():
             "peak": INT32_VALU_PEAK / 1e12,
             "unit": "TOPS (int32 VALU lane-ops/s)",
             "frac": achieved / INT32_VALU_PEAK,
-            "traffic": None,
+            "traffic": float(np.mean(tokens)) * MINHASH_HBM_BYTES_PER_TOKEN,
             "shingle_perm_per_s": float(np.mean([s * wl.num_perm / (t * 1e-3) for s, t in zip(shingles, mh_ms)])),
         },
         "flagged_frac": float(flags[args.warmup:].float().mean().item()),
         "corpus_gen_s": t_gen,
     }
+    if args.copy_bytes:
+        src = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(7)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_bytes"] = args.copy_bytes
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, corpus, min(args.cpu_sample_docs, n_docs))
     print(json.dumps(out), flush=True)

@@ -9,8 +9,10 @@
 
 #if defined(__HIPCC__)
 #define LB_FN __host__ __device__ __forceinline__
+#define LB_MEMBER __host__ __device__ __forceinline__
 #else
 #define LB_FN static inline
+#define LB_MEMBER inline
 #endif
 
 namespace lb {
@@ -56,12 +58,137 @@ LB_FN uint64_t umulhi64(uint64_t x, uint64_t y) {
 // canonical.  R >= p exactly when R + 1 >= 2^61, and R - p has the low word
 // of R plus one (2^61 has a zero low word), so the result is
 //   low32(R) + ((R + 1) >> 61).
-LB_FN uint32_t perm_lo32(uint32_t x, uint32_t a_lo, uint32_t a_hi, uint32_t b_lo, uint32_t b_hi) {
+// With a_hi, b_hi <= 2^29 - 1 and P >> 32 <= 2^32 - 1, Q <= 2^61 - 1, so in
+// fact Q >> 29 < 2^32 and R < 2^61 + 2^32.
+LB_FN uint64_t perm_r(uint32_t x, uint32_t a_lo, uint32_t a_hi, uint32_t b_lo, uint32_t b_hi) {
   const uint64_t P = (uint64_t)a_lo * x + b_lo;
-  const uint64_t Q = (uint64_t)a_hi * x + ((P >> 32) + b_hi);
-  const uint64_t R = ((Q & 0x1FFFFFFFull) << 32) + (uint32_t)P + (Q >> 29);
+  const uint64_t Q = (uint64_t)a_hi * x + b_hi + (P >> 32);
+  // (Q mod 2^29) * 2^32 and P mod 2^32 occupy disjoint bits: one register pair.
+  uint64_t pair = ((Q & 0x1FFFFFFFull) << 32) | (uint32_t)P;
+#if defined(__HIP_DEVICE_COMPILE__)
+  // Keep the pair as one 64-bit register value: without this barrier the
+  // compiler re-associates the sum into two 64-bit adds and extra moves.
+  asm("" : "+v"(pair));
+#endif
+  return pair + (Q >> 29);
+}
+
+LB_FN uint32_t perm_lo32(uint32_t x, uint32_t a_lo, uint32_t a_hi, uint32_t b_lo, uint32_t b_hi) {
+  const uint64_t R = perm_r(x, a_lo, a_hi, b_lo, b_hi);
   return (uint32_t)R + (uint32_t)((R + 1) >> 61);
 }
+
+// Three-input bitwise functions of SHA-1 (FIPS 180-4 §4.1.1).  On gfx950 each
+// is one v_bitop3_b32 (truth tables 0x96 = x^y^z, 0xE8 = majority; both are
+// symmetric, so the operand order does not matter).
+LB_FN uint32_t xor3(uint32_t x, uint32_t y, uint32_t z) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(x, y, z, 0x96);
+#else
+  return x ^ y ^ z;
+#endif
+}
+
+LB_FN uint32_t maj3(uint32_t x, uint32_t y, uint32_t z) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_bitop3_b32(x, y, z, 0xE8);
+#else
+  return (x & y) | (z & (x | y));
+#endif
+}
+
+LB_FN uint32_t ch3(uint32_t x, uint32_t y, uint32_t z) { return z ^ (x & (y ^ z)); }  // v_bfi_b32
+
+// One SHA-1 round t (FIPS 180-4 §6.1.2 step 3) with message word wt.
+template <int T>
+LB_FN void sha1_round(uint32_t &a, uint32_t &b, uint32_t &c, uint32_t &d, uint32_t &e, uint32_t wt) {
+  uint32_t f, K;
+  if constexpr (T < 20) {
+    f = ch3(b, c, d);
+    K = 0x5A827999u;
+  } else if constexpr (T < 40) {
+    f = xor3(b, c, d);
+    K = 0x6ED9EBA1u;
+  } else if constexpr (T < 60) {
+    f = maj3(b, c, d);
+    K = 0x8F1BBCDCu;
+  } else {
+    f = xor3(b, c, d);
+    K = 0xCA62C1D6u;
+  }
+  const uint32_t tmp = rotl32(a, 5) + f + e + (K + wt);
+  e = d;
+  d = c;
+  c = rotl32(b, 30);
+  b = a;
+  a = tmp;
+}
+
+// SHA-1 of one padded block whose words LEN..15 are the padding of a
+// 4*LEN-byte message (0x80000000, zeros, bit length 32*LEN), unrolled at
+// compile time so that schedule terms that are padding constants fold away
+// (W_t = rotl1(W_{t-3} ^ W_{t-8} ^ W_{t-14} ^ W_{t-16}), §6.1.2 step 1).
+template <int LEN>
+struct Sha1Fixed {
+  static constexpr bool is_pad(int i) { return i >= LEN && i < 16; }
+  static constexpr uint32_t pad(int i) { return i == LEN ? 0x80000000u : (i == 15 ? 32u * LEN : 0u); }
+
+  // Message word t: W holds the 16-word ring (initial words 0..LEN-1, then
+  // computed words), written back for t >= 16.
+  template <int T>
+  static LB_MEMBER uint32_t word(uint32_t (&W)[16]) {
+    if constexpr (T < 16) {
+      if constexpr (is_pad(T)) return pad(T);
+      else return W[T];
+    } else {
+      constexpr int i0 = T - 3, i1 = T - 8, i2 = T - 14, i3 = T - 16;
+      // constant part of the XOR and the variable terms
+      constexpr uint32_t cst = (i0 < 16 && is_pad(i0) ? pad(i0) : 0u) ^ (i1 < 16 && is_pad(i1) ? pad(i1) : 0u) ^
+                               (i2 < 16 && is_pad(i2) ? pad(i2) : 0u) ^ (i3 < 16 && is_pad(i3) ? pad(i3) : 0u);
+      constexpr bool v0 = !(i0 < 16 && is_pad(i0)), v1 = !(i1 < 16 && is_pad(i1));
+      constexpr bool v2 = !(i2 < 16 && is_pad(i2)), v3 = !(i3 < 16 && is_pad(i3));
+      constexpr int nv = (int)v0 + (int)v1 + (int)v2 + (int)v3;
+      uint32_t t[4];
+      int k = 0;
+      if constexpr (v0) t[k++] = W[i0 & 15];
+      if constexpr (v1) t[k++] = W[i1 & 15];
+      if constexpr (v2) t[k++] = W[i2 & 15];
+      if constexpr (v3) t[k++] = W[i3 & 15];
+      uint32_t x;
+      if constexpr (nv == 4) {
+        x = xor3(t[0], t[1], t[2]) ^ t[3];
+        if constexpr (cst != 0u) x ^= cst;
+      } else if constexpr (nv == 3) {
+        x = (cst != 0u) ? (xor3(t[0], t[1], t[2]) ^ cst) : xor3(t[0], t[1], t[2]);
+      } else if constexpr (nv == 2) {
+        x = (cst != 0u) ? xor3(t[0], t[1], cst) : (t[0] ^ t[1]);
+      } else if constexpr (nv == 1) {
+        x = t[0] ^ cst;
+      } else {
+        x = cst;
+      }
+      const uint32_t w = rotl32(x, 1);
+      W[T & 15] = w;
+      return w;
+    }
+  }
+
+  template <int T>
+  static LB_MEMBER void rounds(uint32_t (&W)[16], uint32_t &a, uint32_t &b, uint32_t &c, uint32_t &d, uint32_t &e) {
+    if constexpr (T < 80) {
+      const uint32_t wt = word<T>(W);
+      sha1_round<T>(a, b, c, d, e, wt);
+      rounds<T + 1>(W, a, b, c, d, e);
+    }
+  }
+
+  // First four digest bytes read as a little-endian uint32, i.e. bswap(H0).
+  static LB_MEMBER uint32_t h0_le(uint32_t (&W)[16]) {
+    uint32_t a = 0x67452301u, b = 0xEFCDAB89u, c = 0x98BADCFEu, d = 0x10325476u, e = 0xC3D2E1F0u;
+    rounds<0>(W, a, b, c, d, e);
+    return bswap32(0x67452301u + a);
+  }
+};
 
 // SHA-1 (FIPS 180-4 §6.1.2) of one already-padded 64-byte block given as 16
 // big-endian words, from the standard initial state; returns the first four
@@ -74,24 +201,24 @@ LB_FN uint32_t sha1_block_h0_le(uint32_t W[16]) {
     if (t < 16) {
       wt = W[t];
     } else {
-      wt = rotl32(W[(t - 3) & 15] ^ W[(t - 8) & 15] ^ W[(t - 14) & 15] ^ W[t & 15], 1);
+      wt = rotl32(xor3(W[(t - 3) & 15], W[(t - 8) & 15], W[(t - 14) & 15]) ^ W[t & 15], 1);
       W[t & 15] = wt;
     }
     uint32_t f, K;
     if (t < 20) {
-      f = d ^ (b & (c ^ d));
+      f = ch3(b, c, d);
       K = 0x5A827999u;
     } else if (t < 40) {
-      f = b ^ c ^ d;
+      f = xor3(b, c, d);
       K = 0x6ED9EBA1u;
     } else if (t < 60) {
-      f = (b & c) | (d & (b | c));
+      f = maj3(b, c, d);
       K = 0x8F1BBCDCu;
     } else {
-      f = b ^ c ^ d;
+      f = xor3(b, c, d);
       K = 0xCA62C1D6u;
     }
-    const uint32_t T = rotl32(a, 5) + f + e + K + wt;
+    const uint32_t T = rotl32(a, 5) + f + e + (K + wt);
     e = d;
     d = c;
     c = rotl32(b, 30);
@@ -101,10 +228,10 @@ LB_FN uint32_t sha1_block_h0_le(uint32_t W[16]) {
   return bswap32(0x67452301u + a);
 }
 
-// Shingle hash of `len` (1..13) tokens: SHA-1 over their little-endian bytes.
-// The message is 4*len bytes, so the padded block is: the tokens as
+// Shingle hash of LEN (1..13) tokens: SHA-1 over their little-endian bytes.
+// The message is 4*LEN bytes, so the padded block is: the tokens as
 // big-endian words (byte-swapped), the 0x80 terminator word, zeros, and the
-// bit length 32*len in the last word.
+// bit length 32*LEN in the last word.
 template <int LEN>
 LB_FN uint32_t shingle_hash_fixed(const uint32_t *tok) {
   uint32_t W[16];
@@ -112,9 +239,7 @@ LB_FN uint32_t shingle_hash_fixed(const uint32_t *tok) {
   for (int i = 0; i < 16; ++i) W[i] = 0;
 #pragma unroll
   for (int i = 0; i < LEN; ++i) W[i] = bswap32(tok[i]);
-  W[LEN] = 0x80000000u;
-  W[15] = 32u * LEN;
-  return sha1_block_h0_le(W);
+  return Sha1Fixed<LEN>::h0_le(W);
 }
 
 LB_FN uint32_t shingle_hash_var(const uint32_t *tok, uint32_t len) {

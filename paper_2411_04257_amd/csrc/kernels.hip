@@ -167,11 +167,39 @@ __global__ __launch_bounds__(kBlock) void k_minhash(MinhashLaunch A) {
       vm &= ~seg;
       uint64_t sm = seg;
       while (sm) {
-        const int s2 = __ffsll((unsigned long long)sm) - 1;
+        // Two shingles per iteration (the second repeats the first when the
+        // segment has an odd count: min is idempotent), so that the running
+        // minimum takes one v_min3 per permutation for two evaluations.
+        const int s0 = __ffsll((unsigned long long)sm) - 1;
         sm &= sm - 1;
-        const uint32_t xs = __builtin_amdgcn_readlane(x, s2);
+        const int s1 = sm ? __ffsll((unsigned long long)sm) - 1 : s0;
+        sm &= sm - 1;
+        const uint32_t x0 = __builtin_amdgcn_readlane(x, s0);
+        const uint32_t x1 = __builtin_amdgcn_readlane(x, s1);
+        // Common path: the Mersenne-folded R without its canonical
+        // correction, plus one compare per evaluation whose lane mask is
+        // OR-ed on the scalar unit.  R >= p (probability ~2^-29 per
+        // evaluation) sends the wave through the correction.
+        uint64_t R0[PPL], R1[PPL];
+        uint32_t v0[PPL], v1[PPL];
+        uint64_t ge = 0;
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], perm_lo32(xs, al[p], ah[p], bl[p], bh[p]));
+        for (int p = 0; p < PPL; ++p) {
+          R0[p] = perm_r(x0, al[p], ah[p], bl[p], bh[p]);
+          R1[p] = perm_r(x1, al[p], ah[p], bl[p], bh[p]);
+          v0[p] = (uint32_t)R0[p];
+          v1[p] = (uint32_t)R1[p];
+          ge |= __ballot(R0[p] >= kP61) | __ballot(R1[p] >= kP61);
+        }
+        if (ge) {
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+            v0[p] += (uint32_t)((R0[p] + 1) >> 61);
+            v1[p] += (uint32_t)((R1[p] + 1) >> 61);
+          }
+        }
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], min(v0[p], v1[p]));
       }
     }
     dcur = dnext;
