@@ -42,15 +42,24 @@ MINHASH_HBM_BYTES_PER_TOKEN = 1.126e9 / 2.7207e8
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=13)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2", choices=["c2"])
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"])
     ap.add_argument("--cpu-sample-docs", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--qi-mode", type=int, default=0, help="0 automatic, 1 direct, 2 binned query-insert")
+    ap.add_argument("--chunk-docs", type=int, default=None,
+                    help="documents per in-order query-insert chunk (default: the batch)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed steps, one device-to-device copy of this many bytes "
                          "(calibrates the HBM byte counters against a plain copy)")
-    return ap.parse_args()
+    a = ap.parse_args()
+    default_steps = {"c2": (13, 2), "c3": (4, 1), "c4": (20, 2)}[a.workload]
+    if a.steps is None:
+        a.steps = default_steps[0]
+    if a.warmup is None:
+        a.warmup = default_steps[1]
+    return a
 
 
 def shingle_count(lengths, w=5):
@@ -79,6 +88,169 @@ def cpu_baseline(wl, corpus, n_docs):
                       f"MinHash + in-order query-insert, single thread, {dt:.1f} s"}
 
 
+SECTOR = 64  # bytes per random HBM access (one read-modify-write of a 64-B sector per probe)
+
+
+def _events(n):
+    import torch
+
+    return [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(n)]
+
+
+def _index(args, wl, lshbloom):
+    chunk = wl.batch if args.chunk_docs is None else args.chunk_docs
+    # binned workspace: 24 bytes per probe of a chunk
+    budget = 24 * chunk * wl.bands * 40 + (64 << 20)
+    return lshbloom.LSHBloom(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed,
+                             chunk_docs=chunk if args.qi_mode != 1 else 0, qi_mode=args.qi_mode,
+                             workspace_budget=budget)
+
+
+def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
+    """Plain per-batch form over a synthetic corpus: MinHash + query-insert per batch."""
+    B = wl.batch
+    n_batches = args.warmup + args.steps
+    if B * n_batches > wl.n_docs:
+        print(f"warmup + steps exceed the {wl.n_docs // B} full batches of the corpus", file=sys.stderr)
+        sys.exit(2)
+    n_docs = B * n_batches
+    t_gen = time.perf_counter()
+    corpus = synth.make_corpus(wl, device=dev, n_docs=n_docs)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+
+    idx = _index(args, wl, lshbloom)
+    sigs = torch.empty((B, wl.num_perm), dtype=torch.int32, device=dev)
+    flags = torch.empty((n_batches, B), dtype=torch.uint8, device=dev)
+    offs = [corpus.offsets[b * B:(b + 1) * B + 1] for b in range(n_batches)]
+    lengths = torch.diff(corpus.offsets).cpu().numpy()
+
+    for b in range(args.warmup):
+        idx.minhash(offs[b], corpus.tokens, out=sigs)
+        idx.query_insert(sigs, out=flags[b])
+    torch.cuda.synchronize()
+
+    stream = torch.cuda.current_stream()
+    ev = _events(args.steps)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        b = args.warmup + s
+        ev[s][0].record(stream)
+        idx.minhash(offs[b], corpus.tokens, out=sigs)
+        ev[s][1].record(stream)
+        idx.query_insert(sigs, out=flags[b])
+        ev[s][2].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert idx.info()["device_status"] == 0
+
+    mh_ms = [ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)]
+    qi_ms = [ev[s][1].elapsed_time(ev[s][2]) for s in range(args.steps)]
+    timed = range(args.warmup, n_batches)
+    shingles = [shingle_count(lengths[b * B:(b + 1) * B]) for b in timed]
+    tokens = [int(lengths[b * B:(b + 1) * B].sum()) for b in timed]
+    ops = [sh * (OPS_PER_SHINGLE_HASH + wl.num_perm * OPS_PER_SHINGLE_PERM) for sh in shingles]
+    mh_achieved = float(np.mean([o / (t * 1e-3) for o, t in zip(ops, mh_ms)]))
+    probes = B * wl.bands * idx.k
+    qi_achieved = float(np.mean([probes * 2 * SECTOR / (t * 1e-3) for t in qi_ms]))
+    minhash_roof = {
+        "bound": "alu",
+        "kernel": "k_minhash (incl. its 0xFFFFFFFF pre-fill)",
+        "achieved": mh_achieved / 1e12,
+        "peak": INT32_VALU_PEAK / 1e12,
+        "unit": "TOPS (int32 VALU lane-ops/s)",
+        "frac": mh_achieved / INT32_VALU_PEAK,
+        "traffic": float(np.mean(tokens)) * MINHASH_HBM_BYTES_PER_TOKEN if wl.num_perm == 128 else None,
+        "shingle_perm_per_s": float(np.mean([sh * wl.num_perm / (t * 1e-3) for sh, t in zip(shingles, mh_ms)])),
+    }
+    qi_roof = {
+        "bound": "hbm",
+        "kernel": "query-insert (all kernels of a batch's in-order test-and-set)",
+        "achieved": qi_achieved / 1e9,
+        "peak": 8000.0,
+        "unit": "GB/s",
+        "frac": qi_achieved / 8e12,
+        "traffic": None,
+        "probes_per_s": float(np.mean([probes / (t * 1e-3) for t in qi_ms])),
+    }
+    dominant = minhash_roof if np.mean(mh_ms) >= np.mean(qi_ms) else qi_roof
+    res = {
+        "value": args.steps * B / elapsed,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "docs_timed": args.steps * B,
+        "tokens_per_step": float(np.mean(tokens)),
+        "text_GBps": float(np.sum(tokens)) * 4 / elapsed / 1e9,
+        "stage_ms": {"minhash": float(np.mean(mh_ms)), "query_insert": float(np.mean(qi_ms))},
+        "roofline": dominant,
+        "other_rooflines": [r for r in (minhash_roof, qi_roof) if r is not dominant],
+        "flagged_frac": float(flags[args.warmup:].float().mean().item()),
+        "corpus_gen_s": t_gen,
+    }
+    return res, corpus, idx
+
+
+def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
+    """Filter-scale query-insert: batches of precomputed signatures only."""
+    B = wl.batch
+    n_batches = args.warmup + args.steps
+    idx = _index(args, wl, lshbloom)
+    ex = wl.extra
+    t_gen = time.perf_counter()
+    batches = [synth.signature_batch(b * B, B, wl.num_perm, wl.bands, wl.rows, B, ex["repeat_frac"],
+                                     ex["in_batch_frac"], wl.corpus_seed, device=dev) for b in range(n_batches)]
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    flags = torch.empty((n_batches, B), dtype=torch.uint8, device=dev)
+    for b in range(args.warmup):
+        idx.query_insert(batches[b], out=flags[b])
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = _events(args.steps)
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        b = args.warmup + s
+        ev[s][0].record(stream)
+        idx.query_insert(batches[b], out=flags[b])
+        ev[s][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert idx.info()["device_status"] == 0
+    qi_ms = [ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)]
+    probes = B * wl.bands * idx.k
+    ach = float(np.mean([probes * 2 * SECTOR / (t * 1e-3) for t in qi_ms]))
+    rep, _ = synth.signature_repeat_info(args.warmup * B, args.steps * B, wl.bands, B, ex["repeat_frac"],
+                                         ex["in_batch_frac"], wl.corpus_seed, device=dev)
+    fl = flags[args.warmup:].reshape(-1)
+    res = {
+        "value": args.steps * B / elapsed,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "docs_timed": args.steps * B,
+        "stage_ms": {"query_insert": float(np.mean(qi_ms))},
+        "roofline": {
+            "bound": "hbm",
+            "kernel": "query-insert (all kernels of a batch's in-order test-and-set)",
+            "achieved": ach / 1e9, "peak": 8000.0, "unit": "GB/s", "frac": ach / 8e12, "traffic": None,
+            "probes_per_s": float(np.mean([probes / (t * 1e-3) for t in qi_ms])),
+        },
+        "repeats_flagged": float(fl[rep].float().mean().item()),
+        "non_repeats_flagged": float(fl[~rep].float().mean().item()),
+        "filter_bytes": idx.info()["filter_bytes"],
+        "sig_gen_s": t_gen,
+    }
+    return res, None, idx
+
+
+DESCRIPTIONS = {
+    "c2": "plain method on GPU: 1M-doc synthetic corpus (Zipf(1.1)/50k-vocab uint32 tokens, lognormal lengths "
+          "median 3000 sigma 0.8 cap 50000, 20% near-dups J 0.6-0.95), 5-shingles, num_perm 128, 16 bands x 8 rows, "
+          "filters n=1M fp=1e-6, batches of 65,536",
+    "c3": "10M-doc synthetic corpus with Pareto(1.5, min 20, cap 200k) lengths, Zipf(1.1)/50k vocab, 25% near-dups; "
+          "num_perm 256, 32 bands x 8 rows, filters n=100M fp=1e-8 (15.3 GB), batches of 1M",
+    "c4": "filter-scale query-insert: 1B-signature stream of uniform uint32 (256 wide) with 30% one-band repeats, "
+          "32 bands x 8 rows, filters n=1e9 fp=1e-10 per band (191.7 GB in HBM), batches of 1M (timed prefix)",
+}
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -94,101 +266,46 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     wl = synth.WORKLOADS[args.workload]
-    B = wl.batch
-    n_batches = args.warmup + args.steps
-    n_docs = min(wl.n_docs, B * n_batches)
-    if B * n_batches > wl.n_docs:
-        print(f"warmup + steps exceed the {wl.n_docs // B} full batches of the corpus", file=sys.stderr)
-        sys.exit(2)
-    t_gen = time.perf_counter()
-    corpus = synth.make_corpus(wl, device=dev, n_docs=n_docs)
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
-
-    idx = lshbloom.LSHBloom(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
-    sigs = torch.empty((B, wl.num_perm), dtype=torch.int32, device=dev)
-    flags = torch.empty((n_batches, B), dtype=torch.uint8, device=dev)
-    offs = [corpus.offsets[b * B:(b + 1) * B + 1] for b in range(n_batches)]
-    lengths = torch.diff(corpus.offsets).cpu().numpy()
-
-    def step(b):
-        idx.minhash(offs[b], corpus.tokens, out=sigs)
-        idx.query_insert(sigs, out=flags[b])
-
-    for b in range(args.warmup):
-        step(b)
-    torch.cuda.synchronize()
-
-    stream = torch.cuda.current_stream()
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        b = args.warmup + s
-        ev[s][0].record(stream)
-        idx.minhash(offs[b], corpus.tokens, out=sigs)
-        ev[s][1].record(stream)
-        idx.query_insert(sigs, out=flags[b])
-        ev[s][2].record(stream)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-
-    mh_ms = [ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)]
-    qi_ms = [ev[s][1].elapsed_time(ev[s][2]) for s in range(args.steps)]
-    timed = range(args.warmup, n_batches)
-    shingles = [shingle_count(lengths[b * B:(b + 1) * B]) for b in timed]
-    tokens = [int(lengths[b * B:(b + 1) * B].sum()) for b in timed]
-    ops = [s * (OPS_PER_SHINGLE_HASH + wl.num_perm * OPS_PER_SHINGLE_PERM) for s in shingles]
-    achieved = float(np.mean([o / (t * 1e-3) for o, t in zip(ops, mh_ms)]))
-    docs = args.steps * B
-    value = docs / elapsed
-    info = idx.info()
-    assert info["device_status"] == 0
+    if args.workload == "c4":
+        res, corpus, idx = run_signatures(args, wl, torch, np, lshbloom, synth, dev)
+        metric = "signatures/sec query-insert (band Bloom), bit-exact flags"
+        unit = "sigs/s"
+    else:
+        res, corpus, idx = run_corpus(args, wl, torch, np, lshbloom, synth, dev)
+        metric = "docs/sec end-to-end (MinHash+band Bloom), bit-exact flags"
+        unit = "docs/s"
 
     out = {
-        "metric": "docs/sec end-to-end (MinHash+band Bloom), bit-exact flags",
-        "value": value,
-        "unit": "docs/s",
+        "metric": metric,
+        "value": res.pop("value"),
+        "unit": unit,
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": res.pop("ms_per_step"),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": "plain method on GPU: 1M-doc synthetic corpus (Zipf(1.1)/50k-vocab uint32 tokens, "
-                        "lognormal lengths median 3000 sigma 0.8 cap 50000, 20% near-dups J 0.6-0.95), "
-                        "5-shingles, num_perm 128, 16 bands x 8 rows, filters n=1M fp=1e-6, batches of 65,536",
-            "global_batch": B,
-            "docs_timed": docs,
-            "tokens_per_step": float(np.mean(tokens)),
+            "workload": DESCRIPTIONS[args.workload],
+            "global_batch": wl.batch,
+            "docs_timed": res.pop("docs_timed"),
             "parallelism": "single-gpu",
         },
-        "text_GBps": float(np.sum(tokens)) * 4 / elapsed / 1e9,
-        "stage_ms": {"minhash": float(np.mean(mh_ms)), "query_insert": float(np.mean(qi_ms))},
-        "roofline": {
-            "bound": "alu",
-            "kernel": "k_minhash (incl. its 0xFFFFFFFF pre-fill)",
-            "achieved": achieved / 1e12,
-            "peak": INT32_VALU_PEAK / 1e12,
-            "unit": "TOPS (int32 VALU lane-ops/s)",
-            "frac": achieved / INT32_VALU_PEAK,
-            "traffic": float(np.mean(tokens)) * MINHASH_HBM_BYTES_PER_TOKEN,
-            "shingle_perm_per_s": float(np.mean([s * wl.num_perm / (t * 1e-3) for s, t in zip(shingles, mh_ms)])),
-        },
-        "flagged_frac": float(flags[args.warmup:].float().mean().item()),
-        "corpus_gen_s": t_gen,
     }
+    if "tokens_per_step" in res:
+        out["config"]["tokens_per_step"] = res.pop("tokens_per_step")
+    out.update(res)
     if args.copy_bytes:
         src = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device=dev).fill_(7)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_bytes"] = args.copy_bytes
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, corpus, min(args.cpu_sample_docs, n_docs))
+    if corpus is not None and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, corpus, min(args.cpu_sample_docs, corpus.n_docs))
     print(json.dumps(out), flush=True)
 
 

@@ -101,6 +101,10 @@ typedef struct lshbloom_params {
   uint32_t shingle_width; /* w, 1..LSHBLOOM_MAX_SHINGLE_WIDTH; 0 means 5 */
   uint64_t hbm_budget;    /* bytes the handle may allocate; 0 = no limit */
   uint64_t chunk_docs;    /* documents per in-order query-insert chunk; 0 = automatic */
+  uint32_t qi_mode;       /* query-insert algorithm: 0 automatic, 1 direct (first-setter hash table
+                             with device atomics), 2 binned (probes partitioned by bit range; one
+                             workgroup owns each range); results are identical */
+  uint64_t workspace_budget; /* bytes for the binned query-insert's workspace; 0 = 4 GiB */
 } lshbloom_params_t;
 
 typedef struct lshbloom_info {
@@ -110,7 +114,8 @@ typedef struct lshbloom_info {
   uint64_t words_per_band;  /* m_bits / 64 */
   uint64_t filter_bytes;    /* bands * m_bits / 8 */
   uint64_t workspace_bytes; /* device bytes besides the filters */
-  uint64_t chunk_docs;      /* documents per query-insert chunk */
+  uint64_t chunk_docs;      /* documents per direct query-insert chunk */
+  uint64_t binned_chunk_docs; /* documents per binned query-insert chunk */
   double fp_rate;           /* per-band p */
   double p_eff;             /* 1 - (1 - p)^bands (Section 4.3) */
   uint64_t docs_inserted;   /* documents inserted so far (host count of calls) */

@@ -18,6 +18,7 @@
 
 #include "../../include/lshbloom.h"
 #include "kernels.h"
+#include "qi_binned.h"
 
 namespace {
 
@@ -46,6 +47,9 @@ struct SplitMix64 {
 
 constexpr uint64_t kP61 = 0x1FFFFFFFFFFFFFFFull;
 constexpr uint64_t kDefaultTableBytes = 128ull << 20;
+// Calls with at least this many documents use the binned query-insert when
+// the mode is automatic (its fixed cost of ~10 launches pays off there).
+constexpr int64_t kBinnedMinDocs = 4096;
 
 uint64_t next_pow2(uint64_t v) {
   uint64_t p = 1;
@@ -71,6 +75,14 @@ struct lshbloom {
   uint32_t *d_status = nullptr;
   uint64_t chunk_docs = 0;
   uint64_t workspace_bytes = 0;
+  // binned query-insert workspace
+  uint32_t qi_mode = 0;
+  uint64_t bin_chunk = 0;
+  uint64_t bin_counts_cap = 0;  // entries of counts1 / offs1
+  uint64_t bin_supers_cap = 0;
+  uint64_t bin_off2_cap = 0;
+  uint32_t *d_counts1 = nullptr, *d_offs1 = nullptr, *d_super = nullptr, *d_off2 = nullptr;
+  uint64_t *d_rec1 = nullptr, *d_rec2 = nullptr;
   int minhash_waves = 0;
   hipEvent_t last = nullptr;
   bool has_last = false;
@@ -98,6 +110,12 @@ void free_all(lshbloom *h) {
   if (h->d_masks) (void)hipFree(h->d_masks);
   if (h->d_hitb) (void)hipFree(h->d_hitb);
   if (h->d_status) (void)hipFree(h->d_status);
+  if (h->d_counts1) (void)hipFree(h->d_counts1);
+  if (h->d_offs1) (void)hipFree(h->d_offs1);
+  if (h->d_super) (void)hipFree(h->d_super);
+  if (h->d_off2) (void)hipFree(h->d_off2);
+  if (h->d_rec1) (void)hipFree(h->d_rec1);
+  if (h->d_rec2) (void)hipFree(h->d_rec2);
   if (h->last) (void)hipEventDestroy(h->last);
 }
 
@@ -286,7 +304,10 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   // least twice the probes of a chunk.
   const uint64_t probes_per_doc = (uint64_t)prm.bands * k;
   uint64_t table_bytes = kDefaultTableBytes;
-  uint64_t chunk = prm.chunk_docs;
+  // A caller's chunk size applies to the direct algorithm only when it is
+  // selected explicitly; otherwise the direct path (small calls) keeps a
+  // 128 MB table.
+  uint64_t chunk = prm.qi_mode == 1 ? prm.chunk_docs : 0;
   if (chunk == 0) chunk = table_bytes / 8 / (2 * probes_per_doc);
   if (chunk > lb::kMaxChunkDocs) chunk = lb::kMaxChunkDocs;
   if (chunk < 1) chunk = 1;
@@ -294,8 +315,34 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   h->chunk_docs = chunk;
   h->table_slots_max = slots;
 
+  // Binned query-insert: 24 bytes per probe of a chunk (pass-1 records reused
+  // as the published tables, 2 x 8 B, plus the binned records, 8 B).
+  h->qi_mode = prm.qi_mode;
+  if (const char *qm = std::getenv("LSHBLOOM_QI_MODE")) {
+    if (!std::strcmp(qm, "direct")) h->qi_mode = 1;
+    if (!std::strcmp(qm, "binned")) h->qi_mode = 2;
+  }
+  uint64_t bin_chunk = 0, bin_ws = 0;
+  if (h->qi_mode != 1) {
+    const uint64_t budget = prm.workspace_budget ? prm.workspace_budget : (4ull << 30);
+    bin_chunk = prm.chunk_docs ? prm.chunk_docs : budget / (24 * probes_per_doc);
+    if (!prm.chunk_docs) bin_chunk = std::min<uint64_t>(bin_chunk, std::max<uint64_t>(prm.expected_n, 65536));
+    bin_chunk = std::min<uint64_t>(bin_chunk, (1ull << 24) - 1);                 // document index field
+    bin_chunk = std::min<uint64_t>(bin_chunk, 0xFFFFFFFFull / probes_per_doc);   // 32-bit record offsets
+    if (bin_chunk < 1) bin_chunk = 1;
+    const lb::BinnedGeometry g_big = lb::binned_geometry(bin_chunk, prm.bands, k, h->m_bits);
+    const lb::BinnedGeometry g_small = lb::binned_geometry(1, prm.bands, k, h->m_bits);
+    h->bin_supers_cap = std::max<uint64_t>(std::max(g_big.n_supers, g_small.n_supers), 1);
+    h->bin_counts_cap = h->bin_supers_cap * 1536;
+    h->bin_off2_cap = std::max(g_big.bins_per_band, g_small.bins_per_band) * prm.bands + 1;
+    bin_ws = bin_chunk * probes_per_doc * 24 + h->bin_counts_cap * 8 + h->bin_supers_cap * 4 + h->bin_off2_cap * 4;
+  }
+  h->bin_chunk = bin_chunk;
+  const uint64_t hitb_docs = std::max(chunk, bin_chunk);
+
   const uint64_t filter_bytes = h->m_bits / 8 * prm.bands;
-  const uint64_t ws = slots * 8 + chunk * prm.bands * (8 + 8 + 1) + prm.num_perm * sizeof(lb::PermCoef) + 256;
+  const uint64_t ws = slots * 8 + chunk * prm.bands * (8 + 8) + hitb_docs * prm.bands +
+                      prm.num_perm * sizeof(lb::PermCoef) + 256 + bin_ws;
   h->workspace_bytes = ws;
   if (prm.hbm_budget && filter_bytes + ws > prm.hbm_budget) {
     set_err("create: filters (%llu B) + workspace (%llu B) exceed the HBM budget (%llu B)",
@@ -337,7 +384,15 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   LB_ALLOC(h->d_table, slots * 8);
   LB_ALLOC(h->d_keys, chunk * prm.bands * 8);
   LB_ALLOC(h->d_masks, chunk * prm.bands * 8);
-  LB_ALLOC(h->d_hitb, chunk * prm.bands);
+  LB_ALLOC(h->d_hitb, hitb_docs * prm.bands);
+  if (bin_chunk) {
+    LB_ALLOC(h->d_counts1, h->bin_counts_cap * 4);
+    LB_ALLOC(h->d_offs1, h->bin_counts_cap * 4);
+    LB_ALLOC(h->d_super, h->bin_supers_cap * 4);
+    LB_ALLOC(h->d_off2, h->bin_off2_cap * 4);
+    LB_ALLOC(h->d_rec1, bin_chunk * probes_per_doc * 16);
+    LB_ALLOC(h->d_rec2, bin_chunk * probes_per_doc * 8);
+  }
   LB_ALLOC(h->d_coef, prm.num_perm * sizeof(lb::PermCoef));
   LB_ALLOC(h->d_status, 256);
 #undef LB_ALLOC
@@ -420,6 +475,56 @@ int lshbloom_query_insert(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs,
   hipError_t e = begin_ordered(h, s);
   if (e != hipSuccess) return fail_hip(h, e, "query_insert: stream wait");
   const uint64_t pd = (uint64_t)h->prm.bands * h->k;
+  const bool binned = h->bin_chunk && (h->qi_mode == 2 || (h->qi_mode == 0 && n_docs >= kBinnedMinDocs));
+  if (binned) {
+    for (int64_t c0 = 0; c0 < n_docs; c0 += (int64_t)h->bin_chunk) {
+      const int64_t cn = std::min<int64_t>((int64_t)h->bin_chunk, n_docs - c0);
+      const lb::BinnedGeometry G = lb::binned_geometry((uint64_t)cn, h->prm.bands, h->k, h->m_bits);
+      lb::BinnedLaunch a{};
+      a.sigs = d_sigs + c0 * (int64_t)h->prm.num_perm;
+      a.n = cn;
+      a.num_perm = h->prm.num_perm;
+      a.bands = h->prm.bands;
+      a.rows = h->prm.rows;
+      a.k = h->k;
+      a.m_bits = h->m_bits;
+      a.words_per_band = h->words_per_band;
+      a.salt_m = h->salt_m;
+      a.salt1 = h->salt1;
+      a.salt2 = h->salt2;
+      a.filters = h->d_filters;
+      a.bin_bits = G.bin_bits;
+      a.bins_per_band = G.bins_per_band;
+      a.bins_per_super = G.bins_per_super;
+      a.supers_per_band = G.supers_per_band;
+      a.n_supers = G.n_supers;
+      a.items_per_block = G.items_per_block;
+      a.n_blocks1 = G.n_blocks1;
+      a.n_records = (uint32_t)((uint64_t)cn * pd);
+      a.counts1 = h->d_counts1;
+      a.offs1 = h->d_offs1;
+      a.super_tot = h->d_super;
+      a.rec1 = h->d_rec1;
+      a.rec2 = h->d_rec2;
+      a.table = h->d_rec1;
+      a.off2 = h->d_off2;
+      a.hitb = h->d_hitb;
+      a.flags = d_flags + c0;
+      a.status = h->d_status;
+      if ((uint64_t)G.n_supers > h->bin_supers_cap || (uint64_t)G.n_supers * G.n_blocks1 > h->bin_counts_cap ||
+          (uint64_t)h->prm.bands * G.bins_per_band + 1 > h->bin_off2_cap) {
+        set_err("query_insert: binned geometry exceeds the workspace (internal error)");
+        h->poisoned = true;
+        return LSHBLOOM_EHIP;
+      }
+      e = lb::launch_query_insert_binned(a, s);
+      if (e != hipSuccess) return fail_hip(h, e, "query_insert: binned launch");
+    }
+    e = end_ordered(h, s);
+    if (e != hipSuccess) return fail_hip(h, e, "query_insert: event");
+    h->docs_inserted += (uint64_t)n_docs;
+    return LSHBLOOM_OK;
+  }
   for (int64_t c0 = 0; c0 < n_docs; c0 += (int64_t)h->chunk_docs) {
     const int64_t cn = std::min<int64_t>((int64_t)h->chunk_docs, n_docs - c0);
     lb::BloomLaunch a = bloom_args(h, d_sigs + c0 * (int64_t)h->prm.num_perm, cn);
@@ -562,6 +667,7 @@ int lshbloom_info(const lshbloom_t *hc, lshbloom_info_t *out) {
   out->filter_bytes = h->m_bits / 8 * h->prm.bands;
   out->workspace_bytes = h->workspace_bytes;
   out->chunk_docs = h->chunk_docs;
+  out->binned_chunk_docs = h->bin_chunk;
   out->fp_rate = h->prm.fp_rate;
   out->p_eff = -std::expm1((double)h->prm.bands * std::log1p(-h->prm.fp_rate));
   out->docs_inserted = h->docs_inserted;

@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblshbloom.so")
 
 OK, EINVAL, ENOMEM, EHIP, EPOISONED = 0, -1, -2, -3, -4
+QI_AUTO, QI_DIRECT, QI_BINNED = 0, 1, 2
 _CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EPOISONED: "EPOISONED"}
 
 
@@ -38,6 +39,8 @@ class Params(ctypes.Structure):
         ("shingle_width", ctypes.c_uint32),
         ("hbm_budget", ctypes.c_uint64),
         ("chunk_docs", ctypes.c_uint64),
+        ("qi_mode", ctypes.c_uint32),
+        ("workspace_budget", ctypes.c_uint64),
     ]
 
 
@@ -53,6 +56,7 @@ class Info(ctypes.Structure):
         ("filter_bytes", ctypes.c_uint64),
         ("workspace_bytes", ctypes.c_uint64),
         ("chunk_docs", ctypes.c_uint64),
+        ("binned_chunk_docs", ctypes.c_uint64),
         ("fp_rate", ctypes.c_double),
         ("p_eff", ctypes.c_double),
         ("docs_inserted", ctypes.c_uint64),
@@ -149,10 +153,11 @@ class LSHBloom:
     """An LSHBloom index on the current GPU: one Bloom filter per band."""
 
     def __init__(self, num_perm: int, bands: int, rows: int, expected_n: int, fp_rate: float, seed: int = 42,
-                 shingle_width: int = 5, hbm_budget: int = 0, chunk_docs: int = 0):
+                 shingle_width: int = 5, hbm_budget: int = 0, chunk_docs: int = 0, qi_mode: int = 0,
+                 workspace_budget: int = 0):
         L = load()
         p = Params(num_perm, bands, rows, int(expected_n), float(fp_rate), int(seed), shingle_width,
-                   int(hbm_budget), int(chunk_docs))
+                   int(hbm_budget), int(chunk_docs), int(qi_mode), int(workspace_budget))
         self._h = L.lshbloom_create_ex(ctypes.byref(p))
         if not self._h:
             raise LSHBloomError(EINVAL, last_error())

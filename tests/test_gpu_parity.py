@@ -18,6 +18,9 @@ from paper_2411_04257_amd import synth
 
 pytestmark = pytest.mark.gpu
 
+# every query-insert test runs with both algorithms (identical results required)
+QI_MODES = pytest.mark.parametrize("qi_mode", [1, 2], ids=["direct", "binned"])
+
 
 def _to_gpu(offsets, tokens):
     off = torch.as_tensor(np.ascontiguousarray(offsets, dtype=np.int64)).cuda()
@@ -52,13 +55,14 @@ def test_parameters_match_oracle(gpu):
         g.close()
 
 
-def test_c1_end_to_end_bit_exact(gpu):
+@QI_MODES
+def test_c1_end_to_end_bit_exact(gpu, qi_mode):
     """The plain method at its CPU-seconds configuration: 2,000 documents."""
     wl = synth.WORKLOADS["c1"]
     corpus = synth.make_corpus(wl)
     off = corpus.offsets.numpy()
     tok = corpus.tokens.numpy().view(np.uint32)
-    g, o = _pair(gpu, wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
+    g, o = _pair(gpu, wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed, qi_mode=qi_mode)
     want_sigs = o.minhash(off, tok)
     want_flags = o.query_insert(want_sigs)
     doff, dtok = _to_gpu(off, tok)
@@ -148,9 +152,9 @@ def _random_sigs(rng, n, P):
     return rng.integers(0, 2**32, (n, P), dtype=np.uint64).astype(np.uint32)
 
 
-def _qi_case(gpu, sigs, chunk_docs=0, batches=None, **kw):
+def _qi_case(gpu, sigs, chunk_docs=0, batches=None, qi_mode=0, **kw):
     P = sigs.shape[1]
-    g, o = _pair(gpu, num_perm=P, chunk_docs=chunk_docs, **kw)
+    g, o = _pair(gpu, num_perm=P, chunk_docs=chunk_docs, qi_mode=qi_mode, **kw)
     want = o.query_insert(sigs)
     ds = torch.as_tensor(sigs.view(np.int32)).cuda()
     if batches is None:
@@ -168,14 +172,16 @@ def _qi_case(gpu, sigs, chunk_docs=0, batches=None, **kw):
     return want
 
 
-def test_query_insert_identical_documents(gpu):
+@QI_MODES
+def test_query_insert_identical_documents(gpu, qi_mode):
     rng = np.random.default_rng(1)
-    sigs = np.repeat(_random_sigs(rng, 1, 128), 500, axis=0)
-    want = _qi_case(gpu, sigs)
+    sigs = np.repeat(_random_sigs(rng, 1, 128), 5000, axis=0)
+    want = _qi_case(gpu, sigs, qi_mode=qi_mode)
     assert want[0] == 0 and want[1:].all()
 
 
-def test_query_insert_in_batch_repeats(gpu):
+@QI_MODES
+def test_query_insert_in_batch_repeats(gpu, qi_mode):
     """30% of signatures repeat one band of an earlier signature of the same
     batch: those must be flagged, and exactly as the sequential order says."""
     rng = np.random.default_rng(2)
@@ -187,27 +193,29 @@ def test_query_insert_in_batch_repeats(gpu):
         s = int(rng.integers(0, i))
         j = int(rng.integers(0, 16))
         sigs[i, j * r:(j + 1) * r] = sigs[s, j * r:(j + 1) * r]
-    want = _qi_case(gpu, sigs, n=n, fp=1e-6)
+    want = _qi_case(gpu, sigs, n=n, fp=1e-6, qi_mode=qi_mode)
     assert want[rep].all()
 
 
+@QI_MODES
 @pytest.mark.parametrize("chunk_docs", [0, 1, 7, 64, 1000])
-def test_query_insert_heavy_crosstalk_every_chunking(gpu, chunk_docs):
+def test_query_insert_heavy_crosstalk_every_chunking(gpu, chunk_docs, qi_mode):
     """Tiny filters (sized for 300 documents at p = 0.2, fed 3,000): in-batch
     Bloom cross-talk between different keys is frequent; every chunking gives
     the sequential result."""
     rng = np.random.default_rng(9)
     sigs = _random_sigs(rng, 3000, 64)
-    want = _qi_case(gpu, sigs, chunk_docs=chunk_docs, bands=4, rows=8, n=300, fp=0.2)
+    want = _qi_case(gpu, sigs, chunk_docs=chunk_docs, bands=4, rows=8, n=300, fp=0.2, qi_mode=qi_mode)
     assert 0.2 < want.mean() < 0.999
 
 
-def test_query_insert_split_into_calls_and_streams(gpu):
+@QI_MODES
+def test_query_insert_split_into_calls_and_streams(gpu, qi_mode):
     """Document order is host call order, whatever stream each call uses."""
     rng = np.random.default_rng(10)
     sigs = _random_sigs(rng, 2500, 128)
     sigs[1500:1700] = sigs[100:300]
-    g, o = _pair(gpu, n=2500, fp=1e-3)
+    g, o = _pair(gpu, n=2500, fp=1e-3, qi_mode=qi_mode)
     want = o.query_insert(sigs)
     ds = torch.as_tensor(sigs.view(np.int32)).cuda()
     s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
@@ -236,9 +244,10 @@ def test_query_and_insert_only(gpu):
     g.close()
 
 
-def test_write_and_read_filters_round_trip(gpu):
+@QI_MODES
+def test_write_and_read_filters_round_trip(gpu, qi_mode):
     rng = np.random.default_rng(13)
-    g, o = _pair(gpu, n=5000, fp=1e-3)
+    g, o = _pair(gpu, n=5000, fp=1e-3, qi_mode=qi_mode)
     pre = _random_sigs(rng, 3000, 128)
     o.insert(pre)
     words = torch.as_tensor(o.filters().view(np.int64)).cuda()
@@ -284,14 +293,15 @@ def test_invalid_arguments_rejected(gpu):
     g.close()
 
 
-def test_c2_full_batch_prefix_and_samples(gpu):
+@QI_MODES
+def test_c2_full_batch_prefix_and_samples(gpu, qi_mode):
     """A full 65,536-document batch of the 1M-document workload in the
     benchmark's launch configuration: the oracle recomputes a prefix of the
     stream (flags of the prefix depend only on earlier documents) and a random
     sample of signatures one by one."""
     wl = synth.WORKLOADS["c2"]
     corpus = synth.make_corpus(wl, device="cuda", n_docs=wl.batch, seed=wl.corpus_seed)
-    g = gpu.LSHBloom(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
+    g = gpu.LSHBloom(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed, qi_mode=qi_mode)
     sigs = g.minhash(corpus.offsets, corpus.tokens)
     flags = g.query_insert(sigs)
     torch.cuda.synchronize()
