@@ -193,6 +193,58 @@ double lshbloom_p_band_from_eff(double p_eff, uint32_t bands);
 int lshbloom_optimal_bands(double threshold, uint32_t num_perm, double w_fp, double w_fn, uint32_t *bands,
                            uint32_t *rows);
 
+/* ------------------------------------------------------------------------ */
+/* Batched form: a host-to-host pipeline around one handle.                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct lshbloom_pipeline lshbloom_pipeline_t;
+
+typedef struct lshbloom_pipeline_params {
+  uint64_t max_docs;          /* capacity: documents per submitted batch */
+  uint64_t max_tokens;        /* capacity: tokens per submitted batch */
+  uint32_t n_buckets;         /* 1..4 MinHash length buckets; 0 = chosen by the autotuner (or 1) */
+  uint64_t bucket_edges[3];   /* token-length edges: bucket b holds lengths in [edge[b-1], edge[b]) */
+  uint32_t waves_per_cu[4];   /* persistent MinHash waves per compute unit, per bucket; 0 = 16 */
+  uint32_t use_graph;         /* 1: capture each slot's device work in a hipGraph and replay it */
+  uint32_t autotune;          /* 1: on the first batch, time candidate bucket edges and grid sizes */
+  const char *tune_cache;     /* text file for autotuned choices (read, then appended); NULL = none */
+} lshbloom_pipeline_params_t;
+
+typedef struct lshbloom_pipeline_info {
+  uint32_t n_buckets;
+  uint64_t bucket_edges[3];
+  uint32_t waves_per_cu[4];
+  int tuned;
+  float tune_best_ms;          /* MinHash time of the chosen configuration on the tuning batch */
+  uint64_t batches;
+  uint64_t graph_launches, graph_updates, graph_instantiations;
+} lshbloom_pipeline_info_t;
+
+/* Create a pipeline that feeds `h` (which must outlive it).  It owns two
+ * slots of pinned host staging and device buffers sized by the capacities,
+ * and two streams of its own.  NULL on error. */
+lshbloom_pipeline_t *lshbloom_pipeline_create(lshbloom_t *h, const lshbloom_pipeline_params_t *params);
+
+/* Submit one CSR batch from host memory: offsets int64 [n_docs + 1] index
+ * h_tokens (checked on the host: non-decreasing, within max_tokens); the
+ * batch's flags (Section 2.1 decisions, uint8) are written to h_flags by
+ * lshbloom_pipeline_wait of the returned ticket (>= 0), or when the slot is
+ * reused two submissions later.  h_tokens and h_flags must stay valid and
+ * unmodified until then.  Documents are ordered by submission, then index;
+ * the call returns once the batch is enqueued (the host work of the next
+ * batch overlaps this one's GPU work).  Negative return = error code. */
+int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offsets, const uint32_t *h_tokens,
+                                 int64_t n_docs, uint8_t *h_flags);
+
+/* Block until the batch of `ticket` is done and its flags are in its h_flags. */
+int lshbloom_pipeline_wait(lshbloom_pipeline_t *pl, int64_t ticket);
+
+/* Chosen buckets, grid sizes and graph counters. */
+int lshbloom_pipeline_info(const lshbloom_pipeline_t *pl, lshbloom_pipeline_info_t *out);
+
+/* Finish outstanding batches (delivering their flags) and free the pipeline. */
+void lshbloom_pipeline_destroy(lshbloom_pipeline_t *pl);
+
 /* Message for the calling thread's last failure ("" if none). */
 const char *lshbloom_last_error(void);
 

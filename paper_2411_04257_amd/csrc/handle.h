@@ -1,0 +1,62 @@
+// Internal definition of the LSHBloom handle, shared by the C-ABI entry
+// points and the batched pipeline.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+
+#include "../../include/lshbloom.h"
+#include "kernels.h"
+#include "qi_binned.h"
+
+struct lshbloom {
+  lshbloom_params_t prm;
+  uint64_t m_bits = 0, words_per_band = 0;
+  uint32_t k = 0;
+  uint64_t salt_m = 0, salt1 = 0, salt2 = 0;
+  int device = 0;
+  lb::PermCoef *d_coef = nullptr;
+  uint64_t *d_filters = nullptr;
+  uint64_t *d_table = nullptr;
+  uint64_t table_slots_max = 0;
+  uint64_t *d_keys = nullptr;
+  uint64_t *d_masks = nullptr;
+  uint8_t *d_hitb = nullptr;
+  uint32_t *d_status = nullptr;
+  uint64_t chunk_docs = 0;
+  uint64_t workspace_bytes = 0;
+  // binned query-insert workspace
+  uint32_t qi_mode = 0;
+  uint64_t bin_chunk = 0;
+  uint64_t bin_counts_cap = 0;  // entries of counts1 / offs1
+  uint64_t bin_supers_cap = 0;
+  uint64_t bin_off2_cap = 0;
+  uint32_t *d_counts1 = nullptr, *d_offs1 = nullptr, *d_super = nullptr, *d_off2 = nullptr;
+  uint64_t *d_rec1 = nullptr, *d_rec2 = nullptr;
+  int minhash_waves = 0;
+  hipEvent_t last = nullptr;
+  bool has_last = false;
+  bool poisoned = false;
+  uint64_t docs_inserted = 0;
+  uint64_t calls = 0;
+  int64_t fault_at = -1;  // host-forced failure of the n-th filter call (testing)
+  std::mutex mu;
+};
+
+namespace lbh {
+
+void set_err(const char *fmt, ...);
+int fail_hip(lshbloom *h, hipError_t e, const char *what);
+// Order the work enqueued next on s after the handle's previous filter call,
+// and record the end of that work as the handle's new last call.
+hipError_t begin_ordered(lshbloom *h, hipStream_t s);
+hipError_t end_ordered(lshbloom *h, hipStream_t s);
+int check_ready(lshbloom *h);
+// Enqueue the in-order query-insert of n signatures on s (no locking, no
+// ordering events, no counters); the algorithm follows the handle's mode.
+// Returns LSHBLOOM_OK or an error code (message set, handle poisoned on a
+// HIP error).
+int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n, uint8_t *d_flags, hipStream_t s);
+
+}  // namespace lbh

@@ -12,6 +12,8 @@ struct PermCoef {
 };
 
 struct MinhashLaunch {
+  // Document boundaries in the position space the persistent grid splits:
+  // document d covers positions [offsets[d], offsets[d+1]).
   const int64_t *offsets;
   const uint32_t *tokens;
   int64_t n_docs;
@@ -20,6 +22,11 @@ struct MinhashLaunch {
   uint32_t num_perm;
   uint32_t w;
   int waves;  // total waves of the persistent grid (multiple of 4)
+  // Optional indirection (length buckets): the token of position p of
+  // document d is tokens[p + tok_shift[d]] and its signature row is
+  // row_ids[d]; both null means identity.
+  const int64_t *tok_shift;
+  const int64_t *row_ids;
 };
 
 struct BloomLaunch {

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(kBlock) void k_minhash(MinhashLaunch A) {
     const int64_t s0 = A.offsets[d], e0 = A.offsets[d + 1];
     const int64_t last = (e0 - s0 >= w) ? e0 - w : s0;
     const bool inside = s0 >= r0 && last < r1;
-    uint32_t *row = A.sigs + d * (int64_t)P;
+    uint32_t *row = A.sigs + (A.row_ids ? A.row_ids[d] : d) * (int64_t)P;
 #pragma unroll
     for (int p = 0; p < PPL; ++p) {
       const uint32_t i = (uint32_t)p * 64u + (uint32_t)lane;
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(kBlock) void k_minhash(MinhashLaunch A) {
     const bool valid = in_range && pos >= ds && pos < de && L > 0 && ((L >= w) ? (pos <= de - w) : (pos == ds));
     uint32_t x = 0;
     if (valid) {
-      const uint32_t *tp = A.tokens + pos;
+      const uint32_t *tp = A.tokens + pos + (A.tok_shift ? A.tok_shift[doc] : 0);
       if (WFIX && L >= w)
         x = shingle_hash_fixed<(WFIX ? WFIX : 1)>(tp);
       else

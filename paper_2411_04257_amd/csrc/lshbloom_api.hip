@@ -16,14 +16,13 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lshbloom.h"
-#include "kernels.h"
-#include "qi_binned.h"
+#include "handle.h"
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
+namespace lbh {
 void set_err(const char *fmt, ...) {
   char buf[512];
   va_list ap;
@@ -32,6 +31,10 @@ void set_err(const char *fmt, ...) {
   va_end(ap);
   g_err = buf;
 }
+}  // namespace lbh
+
+namespace {
+using lbh::set_err;
 
 // SplitMix64 stream (Steele, Lea & Flood 2014).
 struct SplitMix64 {
@@ -59,47 +62,20 @@ uint64_t next_pow2(uint64_t v) {
 
 }  // namespace
 
-struct lshbloom {
-  lshbloom_params_t prm;
-  uint64_t m_bits = 0, words_per_band = 0;
-  uint32_t k = 0;
-  uint64_t salt_m = 0, salt1 = 0, salt2 = 0;
-  int device = 0;
-  lb::PermCoef *d_coef = nullptr;
-  uint64_t *d_filters = nullptr;
-  uint64_t *d_table = nullptr;
-  uint64_t table_slots_max = 0;
-  uint64_t *d_keys = nullptr;
-  uint64_t *d_masks = nullptr;
-  uint8_t *d_hitb = nullptr;
-  uint32_t *d_status = nullptr;
-  uint64_t chunk_docs = 0;
-  uint64_t workspace_bytes = 0;
-  // binned query-insert workspace
-  uint32_t qi_mode = 0;
-  uint64_t bin_chunk = 0;
-  uint64_t bin_counts_cap = 0;  // entries of counts1 / offs1
-  uint64_t bin_supers_cap = 0;
-  uint64_t bin_off2_cap = 0;
-  uint32_t *d_counts1 = nullptr, *d_offs1 = nullptr, *d_super = nullptr, *d_off2 = nullptr;
-  uint64_t *d_rec1 = nullptr, *d_rec2 = nullptr;
-  int minhash_waves = 0;
-  hipEvent_t last = nullptr;
-  bool has_last = false;
-  bool poisoned = false;
-  uint64_t docs_inserted = 0;
-  uint64_t calls = 0;
-  int64_t fault_at = -1;  // host-forced failure of the n-th filter call (testing)
-  std::mutex mu;
-};
 
-namespace {
+
+namespace lbh {
 
 int fail_hip(lshbloom *h, hipError_t e, const char *what) {
   set_err("%s: %s", what, hipGetErrorString(e));
   if (h) h->poisoned = true;
   return LSHBLOOM_EHIP;
 }
+
+}  // namespace lbh
+
+namespace {
+using lbh::fail_hip;
 
 void free_all(lshbloom *h) {
   if (!h) return;
@@ -119,6 +95,9 @@ void free_all(lshbloom *h) {
   if (h->last) (void)hipEventDestroy(h->last);
 }
 
+}  // namespace
+
+namespace lbh {
 // Order this call after the handle's previous filter call.
 hipError_t begin_ordered(lshbloom *h, hipStream_t s) {
   if (h->has_last) return hipStreamWaitEvent(s, h->last, 0);
@@ -142,6 +121,13 @@ int check_ready(lshbloom *h) {
   }
   return LSHBLOOM_OK;
 }
+
+}  // namespace lbh
+
+namespace {
+using lbh::begin_ordered;
+using lbh::check_ready;
+using lbh::end_ordered;
 
 bool forced_fault(lshbloom *h) {
   h->calls += 1;
@@ -177,6 +163,72 @@ lb::BloomLaunch bloom_args(lshbloom *h, const uint32_t *sigs, int64_t n) {
 }
 
 }  // namespace
+
+namespace lbh {
+
+int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags, hipStream_t s) {
+  hipError_t e;
+  const uint64_t pd = (uint64_t)h->prm.bands * h->k;
+  const bool binned = h->bin_chunk && (h->qi_mode == 2 || (h->qi_mode == 0 && n_docs >= kBinnedMinDocs));
+  if (binned) {
+    for (int64_t c0 = 0; c0 < n_docs; c0 += (int64_t)h->bin_chunk) {
+      const int64_t cn = std::min<int64_t>((int64_t)h->bin_chunk, n_docs - c0);
+      const lb::BinnedGeometry G = lb::binned_geometry((uint64_t)cn, h->prm.bands, h->k, h->m_bits);
+      lb::BinnedLaunch a{};
+      a.sigs = d_sigs + c0 * (int64_t)h->prm.num_perm;
+      a.n = cn;
+      a.num_perm = h->prm.num_perm;
+      a.bands = h->prm.bands;
+      a.rows = h->prm.rows;
+      a.k = h->k;
+      a.m_bits = h->m_bits;
+      a.words_per_band = h->words_per_band;
+      a.salt_m = h->salt_m;
+      a.salt1 = h->salt1;
+      a.salt2 = h->salt2;
+      a.filters = h->d_filters;
+      a.bin_bits = G.bin_bits;
+      a.bins_per_band = G.bins_per_band;
+      a.bins_per_super = G.bins_per_super;
+      a.supers_per_band = G.supers_per_band;
+      a.n_supers = G.n_supers;
+      a.items_per_block = G.items_per_block;
+      a.n_blocks1 = G.n_blocks1;
+      a.n_records = (uint32_t)((uint64_t)cn * pd);
+      a.counts1 = h->d_counts1;
+      a.offs1 = h->d_offs1;
+      a.super_tot = h->d_super;
+      a.rec1 = h->d_rec1;
+      a.rec2 = h->d_rec2;
+      a.table = h->d_rec1;
+      a.off2 = h->d_off2;
+      a.hitb = h->d_hitb;
+      a.flags = d_flags + c0;
+      a.status = h->d_status;
+      if ((uint64_t)G.n_supers > h->bin_supers_cap || (uint64_t)G.n_supers * G.n_blocks1 > h->bin_counts_cap ||
+          (uint64_t)h->prm.bands * G.bins_per_band + 1 > h->bin_off2_cap) {
+        set_err("query_insert: binned geometry exceeds the workspace (internal error)");
+        h->poisoned = true;
+        return LSHBLOOM_EHIP;
+      }
+      e = lb::launch_query_insert_binned(a, s);
+      if (e != hipSuccess) return fail_hip(h, e, "query_insert: binned launch");
+    }
+    return LSHBLOOM_OK;
+  }
+  for (int64_t c0 = 0; c0 < n_docs; c0 += (int64_t)h->chunk_docs) {
+    const int64_t cn = std::min<int64_t>((int64_t)h->chunk_docs, n_docs - c0);
+    lb::BloomLaunch a = bloom_args(h, d_sigs + c0 * (int64_t)h->prm.num_perm, cn);
+    a.flags = d_flags + c0;
+    const uint64_t slots = std::min<uint64_t>(h->table_slots_max, next_pow2(std::max<uint64_t>(1024, 2 * cn * pd)));
+    a.table_mask = slots - 1;
+    e = lb::launch_query_insert_chunk(a, slots, s);
+    if (e != hipSuccess) return fail_hip(h, e, "query_insert: launch");
+  }
+  return LSHBLOOM_OK;
+}
+
+}  // namespace lbh
 
 extern "C" {
 
@@ -474,66 +526,8 @@ int lshbloom_query_insert(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs,
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = begin_ordered(h, s);
   if (e != hipSuccess) return fail_hip(h, e, "query_insert: stream wait");
-  const uint64_t pd = (uint64_t)h->prm.bands * h->k;
-  const bool binned = h->bin_chunk && (h->qi_mode == 2 || (h->qi_mode == 0 && n_docs >= kBinnedMinDocs));
-  if (binned) {
-    for (int64_t c0 = 0; c0 < n_docs; c0 += (int64_t)h->bin_chunk) {
-      const int64_t cn = std::min<int64_t>((int64_t)h->bin_chunk, n_docs - c0);
-      const lb::BinnedGeometry G = lb::binned_geometry((uint64_t)cn, h->prm.bands, h->k, h->m_bits);
-      lb::BinnedLaunch a{};
-      a.sigs = d_sigs + c0 * (int64_t)h->prm.num_perm;
-      a.n = cn;
-      a.num_perm = h->prm.num_perm;
-      a.bands = h->prm.bands;
-      a.rows = h->prm.rows;
-      a.k = h->k;
-      a.m_bits = h->m_bits;
-      a.words_per_band = h->words_per_band;
-      a.salt_m = h->salt_m;
-      a.salt1 = h->salt1;
-      a.salt2 = h->salt2;
-      a.filters = h->d_filters;
-      a.bin_bits = G.bin_bits;
-      a.bins_per_band = G.bins_per_band;
-      a.bins_per_super = G.bins_per_super;
-      a.supers_per_band = G.supers_per_band;
-      a.n_supers = G.n_supers;
-      a.items_per_block = G.items_per_block;
-      a.n_blocks1 = G.n_blocks1;
-      a.n_records = (uint32_t)((uint64_t)cn * pd);
-      a.counts1 = h->d_counts1;
-      a.offs1 = h->d_offs1;
-      a.super_tot = h->d_super;
-      a.rec1 = h->d_rec1;
-      a.rec2 = h->d_rec2;
-      a.table = h->d_rec1;
-      a.off2 = h->d_off2;
-      a.hitb = h->d_hitb;
-      a.flags = d_flags + c0;
-      a.status = h->d_status;
-      if ((uint64_t)G.n_supers > h->bin_supers_cap || (uint64_t)G.n_supers * G.n_blocks1 > h->bin_counts_cap ||
-          (uint64_t)h->prm.bands * G.bins_per_band + 1 > h->bin_off2_cap) {
-        set_err("query_insert: binned geometry exceeds the workspace (internal error)");
-        h->poisoned = true;
-        return LSHBLOOM_EHIP;
-      }
-      e = lb::launch_query_insert_binned(a, s);
-      if (e != hipSuccess) return fail_hip(h, e, "query_insert: binned launch");
-    }
-    e = end_ordered(h, s);
-    if (e != hipSuccess) return fail_hip(h, e, "query_insert: event");
-    h->docs_inserted += (uint64_t)n_docs;
-    return LSHBLOOM_OK;
-  }
-  for (int64_t c0 = 0; c0 < n_docs; c0 += (int64_t)h->chunk_docs) {
-    const int64_t cn = std::min<int64_t>((int64_t)h->chunk_docs, n_docs - c0);
-    lb::BloomLaunch a = bloom_args(h, d_sigs + c0 * (int64_t)h->prm.num_perm, cn);
-    a.flags = d_flags + c0;
-    const uint64_t slots = std::min<uint64_t>(h->table_slots_max, next_pow2(std::max<uint64_t>(1024, 2 * cn * pd)));
-    a.table_mask = slots - 1;
-    e = lb::launch_query_insert_chunk(a, slots, s);
-    if (e != hipSuccess) return fail_hip(h, e, "query_insert: launch");
-  }
+  rc = lbh::qi_enqueue(h, d_sigs, n_docs, d_flags, s);
+  if (rc) return rc;
   e = end_ordered(h, s);
   if (e != hipSuccess) return fail_hip(h, e, "query_insert: event");
   h->docs_inserted += (uint64_t)n_docs;

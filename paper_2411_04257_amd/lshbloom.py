@@ -66,11 +66,40 @@ class Info(ctypes.Structure):
     ]
 
 
+class PipelineParams(ctypes.Structure):
+    _fields_ = [
+        ("max_docs", ctypes.c_uint64),
+        ("max_tokens", ctypes.c_uint64),
+        ("n_buckets", ctypes.c_uint32),
+        ("bucket_edges", ctypes.c_uint64 * 3),
+        ("waves_per_cu", ctypes.c_uint32 * 4),
+        ("use_graph", ctypes.c_uint32),
+        ("autotune", ctypes.c_uint32),
+        ("tune_cache", ctypes.c_char_p),
+    ]
+
+
+class PipelineInfo(ctypes.Structure):
+    _fields_ = [
+        ("n_buckets", ctypes.c_uint32),
+        ("bucket_edges", ctypes.c_uint64 * 3),
+        ("waves_per_cu", ctypes.c_uint32 * 4),
+        ("tuned", ctypes.c_int),
+        ("tune_best_ms", ctypes.c_float),
+        ("batches", ctypes.c_uint64),
+        ("graph_launches", ctypes.c_uint64),
+        ("graph_updates", ctypes.c_uint64),
+        ("graph_instantiations", ctypes.c_uint64),
+    ]
+
+
 # Every symbol the header declares.
 EXPORTS = [
     "lshbloom_create", "lshbloom_create_ex", "lshbloom_destroy", "lshbloom_minhash", "lshbloom_query_insert",
     "lshbloom_query", "lshbloom_insert", "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters",
     "lshbloom_info", "lshbloom_p_band_from_eff", "lshbloom_optimal_bands", "lshbloom_last_error",
+    "lshbloom_pipeline_create", "lshbloom_pipeline_submit", "lshbloom_pipeline_wait", "lshbloom_pipeline_info",
+    "lshbloom_pipeline_destroy",
 ]
 
 _lib = None
@@ -103,6 +132,16 @@ def load(path: str = LIB_PATH):
     L.lshbloom_p_band_from_eff.restype = ctypes.c_double
     L.lshbloom_optimal_bands.argtypes = [ctypes.c_double, u32, ctypes.c_double, ctypes.c_double,
                                          ctypes.POINTER(u32), ctypes.POINTER(u32)]
+    L.lshbloom_pipeline_create.argtypes = [vp, ctypes.POINTER(PipelineParams)]
+    L.lshbloom_pipeline_create.restype = vp
+    L.lshbloom_pipeline_submit.argtypes = [vp, vp, vp, i64, vp]
+    L.lshbloom_pipeline_submit.restype = i64
+    L.lshbloom_pipeline_wait.argtypes = [vp, i64]
+    L.lshbloom_pipeline_wait.restype = ctypes.c_int
+    L.lshbloom_pipeline_info.argtypes = [vp, ctypes.POINTER(PipelineInfo)]
+    L.lshbloom_pipeline_info.restype = ctypes.c_int
+    L.lshbloom_pipeline_destroy.argtypes = [vp]
+    L.lshbloom_pipeline_destroy.restype = None
     L.lshbloom_last_error.argtypes = []
     L.lshbloom_last_error.restype = ctypes.c_char_p
     for name in ("lshbloom_minhash", "lshbloom_query_insert", "lshbloom_query", "lshbloom_insert",
@@ -255,3 +294,73 @@ class LSHBloom:
         if sigs.dim() != 2 or sigs.shape[1] != self.num_perm:
             raise ValueError(f"signatures must have shape [n, {self.num_perm}]")
         return int(sigs.shape[0])
+
+
+class Pipeline:
+    """Batched form: host CSR batches in, host flags out, through one index.
+
+    Length-bucketed persistent MinHash, in-order query-insert, two slots so
+    that consecutive batches overlap, optional hipGraph replay and autotuning
+    (all inside the C library)."""
+
+    def __init__(self, index: LSHBloom, max_docs: int, max_tokens: int, n_buckets: int = 0,
+                 bucket_edges=(0, 0, 0), waves_per_cu=(0, 0, 0, 0), use_graph: bool = True,
+                 autotune: bool = True, tune_cache: str | None = None):
+        L = load()
+        self.index = index
+        self._cache = tune_cache.encode() if tune_cache else None
+        p = PipelineParams(int(max_docs), int(max_tokens), int(n_buckets),
+                           (ctypes.c_uint64 * 3)(*[int(e) for e in bucket_edges]),
+                           (ctypes.c_uint32 * 4)(*[int(w) for w in waves_per_cu]),
+                           int(bool(use_graph)), int(bool(autotune)), self._cache)
+        self._p = L.lshbloom_pipeline_create(ctypes.c_void_p(index._h), ctypes.byref(p))
+        if not self._p:
+            raise LSHBloomError(EINVAL, last_error())
+        self._keep = {}
+
+    def submit(self, offsets, tokens, flags_out) -> int:
+        """offsets: int64 host array [n+1]; tokens: uint32/int32 host array;
+        flags_out: uint8 host array [n] (filled when the ticket completes).
+        numpy arrays or CPU torch tensors (pinned ones are copied by DMA)."""
+        import numpy as np
+
+        def ptr(a):
+            if isinstance(a, torch.Tensor):
+                if a.is_cuda or not a.is_contiguous():
+                    raise ValueError("pipeline buffers must be contiguous host tensors")
+                return a.data_ptr()
+            if not (isinstance(a, np.ndarray) and a.flags["C_CONTIGUOUS"]):
+                raise ValueError("pipeline buffers must be contiguous numpy arrays or host tensors")
+            return a.ctypes.data
+
+        n = (offsets.numel() if isinstance(offsets, torch.Tensor) else len(offsets)) - 1
+        t = load().lshbloom_pipeline_submit(self._p, ctypes.c_void_p(ptr(offsets)), ctypes.c_void_p(ptr(tokens)),
+                                            n, ctypes.c_void_p(ptr(flags_out)))
+        if t < 0:
+            raise LSHBloomError(int(t), last_error())
+        self._keep[t] = (offsets, tokens, flags_out)  # keep the buffers alive until waited
+        return int(t)
+
+    def wait(self, ticket: int) -> None:
+        _check(load().lshbloom_pipeline_wait(self._p, ticket))
+        self._keep.pop(ticket, None)
+
+    def info(self) -> dict:
+        inf = PipelineInfo()
+        _check(load().lshbloom_pipeline_info(self._p, ctypes.byref(inf)))
+        d = {name: getattr(inf, name) for name, _ in PipelineInfo._fields_}
+        d["bucket_edges"] = list(d["bucket_edges"])
+        d["waves_per_cu"] = list(d["waves_per_cu"])
+        return d
+
+    def close(self):
+        if getattr(self, "_p", None):
+            load().lshbloom_pipeline_destroy(self._p)
+            self._p = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
