@@ -44,17 +44,24 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--loads", default="2000,10000,50000,250000,1000000,2000000",
+                    help="c5: offered loads in docs/s")
+    ap.add_argument("--preload", type=int, default=None, help="c5: documents inserted before serving")
     ap.add_argument("--cpu-sample-docs", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--qi-mode", type=int, default=0, help="0 automatic, 1 direct, 2 binned query-insert")
+    ap.add_argument("--form", default="plain", choices=["plain", "batched"],
+                    help="plain: per-batch calls on HBM-resident inputs; batched: the host-to-host pipeline "
+                         "(length buckets, overlapping slots, hipGraph, autotuner) compared with per-batch "
+                         "calls that copy the same host batches")
     ap.add_argument("--chunk-docs", type=int, default=None,
                     help="documents per in-order query-insert chunk (default: the batch)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed steps, one device-to-device copy of this many bytes "
                          "(calibrates the HBM byte counters against a plain copy)")
     a = ap.parse_args()
-    default_steps = {"c2": (13, 2), "c3": (4, 1), "c4": (20, 2)}[a.workload]
+    default_steps = {"c2": (13, 2), "c3": (4, 1), "c4": (20, 2), "c5": (0, 0)}[a.workload]
     if a.steps is None:
         a.steps = default_steps[0]
     if a.warmup is None:
@@ -189,6 +196,85 @@ def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
     return res, corpus, idx
 
 
+def run_batched(args, wl, torch, np, lshbloom, synth, dev):
+    """Batched form: host CSR batches through the pipeline, against the plain
+    per-batch calls fed the same host batches (H2D, MinHash, query-insert,
+    D2H, one batch at a time), each with its own index."""
+    B = wl.batch
+    n_batches = args.warmup + args.steps
+    if B * n_batches > wl.n_docs:
+        print(f"warmup + steps exceed the {wl.n_docs // B} full batches of the corpus", file=sys.stderr)
+        sys.exit(2)
+    t_gen = time.perf_counter()
+    corpus = synth.make_corpus(wl, device=dev, n_docs=B * n_batches)
+    h_off = corpus.offsets.cpu().pin_memory()
+    h_tok = corpus.tokens.cpu().pin_memory()
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    lengths = torch.diff(corpus.offsets).cpu().numpy()
+    max_tok = int(max(lengths[b * B:(b + 1) * B].sum() for b in range(n_batches)))
+    del corpus
+
+    # batched form
+    idx = _index(args, wl, lshbloom)
+    pl = lshbloom.Pipeline(idx, max_docs=B, max_tokens=max_tok, use_graph=True, autotune=True)
+    flags = torch.zeros((n_batches, B), dtype=torch.uint8).pin_memory()
+    offs = [h_off[b * B:(b + 1) * B + 1].clone().pin_memory() for b in range(n_batches)]
+    for b in range(args.warmup):
+        pl.wait(pl.submit(offs[b], h_tok, flags[b]))
+    t0 = time.perf_counter()
+    tickets = [pl.submit(offs[b], h_tok, flags[b]) for b in range(args.warmup, n_batches)]
+    for t in tickets:
+        pl.wait(t)
+    elapsed = time.perf_counter() - t0
+    info = pl.info()
+    pl.close()
+    assert idx.info()["device_status"] == 0
+    batched_flags = flags[args.warmup:].clone()
+    idx.close()
+    del idx
+
+    # plain per-batch calls on the same host batches
+    idx = _index(args, wl, lshbloom)
+    sigs = torch.empty((B, wl.num_perm), dtype=torch.int32, device=dev)
+    pflags = torch.zeros((n_batches, B), dtype=torch.uint8).pin_memory()
+
+    def plain(b):
+        o = offs[b]
+        doff = (o - o[0]).to(dev, non_blocking=True)
+        dtok = h_tok[int(o[0]):int(o[-1])].to(dev, non_blocking=True)
+        idx.minhash(doff, dtok, out=sigs)
+        pflags[b].copy_(idx.query_insert(sigs), non_blocking=True)
+        torch.cuda.synchronize()
+
+    for b in range(args.warmup):
+        plain(b)
+    t1 = time.perf_counter()
+    for b in range(args.warmup, n_batches):
+        plain(b)
+    plain_elapsed = time.perf_counter() - t1
+    assert idx.info()["device_status"] == 0
+    same = bool(torch.equal(batched_flags, pflags[args.warmup:]))
+    idx.close()
+    tokens = [int(lengths[b * B:(b + 1) * B].sum()) for b in range(args.warmup, n_batches)]
+    res = {
+        "value": args.steps * B / elapsed,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "docs_timed": args.steps * B,
+        "tokens_per_step": float(np.mean(tokens)),
+        "text_GBps": float(np.sum(tokens)) * 4 / elapsed / 1e9,
+        "form": "batched (host CSR in, host flags out; length buckets, 2 overlapping slots, hipGraph, autotuner)",
+        "plain_per_batch_from_host": {"value": args.steps * B / plain_elapsed,
+                                      "ms_per_step": plain_elapsed * 1e3 / args.steps},
+        "speedup_vs_plain_from_host": plain_elapsed / elapsed,
+        "flags_identical_to_plain": same,
+        "pipeline": info,
+        "flagged_frac": float(batched_flags.float().mean().item()),
+        "corpus_gen_s": t_gen,
+    }
+    return res, None, None
+
+
 def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
     """Filter-scale query-insert: batches of precomputed signatures only."""
     B = wl.batch
@@ -240,6 +326,81 @@ def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
     return res, None, idx
 
 
+def run_serve(args, wl, torch, np, lshbloom, synth, dev):
+    """Served form: Poisson request streams at several offered loads against
+    filters preloaded with 1e8 documents; continuous batching vs one request
+    at a time (the plain per-batch form).  Every run starts from the same
+    preloaded filter state (restored from a device snapshot) and serves the
+    same documents."""
+    import copy
+
+    from paper_2411_04257_amd import serve
+
+    loads = [float(x) for x in args.loads.split(",")]
+    n_reqs = [int(max(40, min(1000, ld / 100))) for ld in loads]
+    preload_n = wl.extra["preload"] if args.preload is None else args.preload
+    rng = np.random.default_rng(wl.corpus_seed)
+    warm = serve.poisson_requests(8, 10000.0, wl.extra["req_min"], wl.extra["req_max"], 0, rng)
+    sizes = serve.poisson_requests(max(n_reqs), 1.0, wl.extra["req_min"], wl.extra["req_max"], warm[-1].hi, rng)
+    n_docs = sizes[-1].hi
+    t_gen = time.perf_counter()
+    corpus = synth.make_corpus(wl, device=dev, n_docs=n_docs)
+    h_off = corpus.offsets.cpu().pin_memory()
+    h_tok = corpus.tokens.cpu().pin_memory()
+    del corpus
+    t_gen = time.perf_counter() - t_gen
+    max_docs = 16384
+    max_tokens = int(max_docs * 8000)
+
+    idx_b = lshbloom.LSHBloom(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
+    idx_p = lshbloom.LSHBloom(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
+    t_pre = time.perf_counter()
+    serve.preload(idx_b, preload_n, 1)
+    t_pre = time.perf_counter() - t_pre
+    snap = idx_b.read_filters()
+    srv = serve.Server(idx_b, max_docs, max_tokens, hbm_budget=2 << 30)
+    plain = serve.PlainServer(idx_p, max_docs, max_tokens)
+    fb = torch.zeros(n_docs, dtype=torch.uint8).pin_memory()
+    fp_ = torch.zeros(n_docs, dtype=torch.uint8).pin_memory()
+    rows = []
+    for ld, nr in [(10000.0, None)] + list(zip(loads, n_reqs)):
+        if nr is None:
+            reqs = warm  # warm-up stream: first-use costs, not reported
+        else:
+            base = serve.poisson_requests(nr, ld, wl.extra["req_min"], wl.extra["req_max"], 0,
+                                          np.random.default_rng(int(ld)))
+            reqs = [serve.Request(q.rid, b.arrival, q.lo, q.hi) for q, b in zip(sizes[:nr], base)]
+        for idx in (idx_b, idx_p):
+            idx.write_filters(snap, docs_inserted=preload_n)
+        torch.cuda.synchronize()
+        rb = srv.run(copy.deepcopy(reqs), h_off, h_tok, fb).summary()
+        rp = plain.run(copy.deepcopy(reqs), h_off, h_tok, fp_).summary()
+        if nr is None:
+            continue
+        lo, hi = reqs[0].lo, reqs[-1].hi
+        rows.append({"offered_docs_per_s": ld, "requests": len(reqs), "docs": int(hi - lo),
+                     "tokens": int(h_off[hi] - h_off[lo]),
+                     "continuous_batching": rb, "plain_one_request_per_batch": rp,
+                     "flags_identical": bool(torch.equal(fb[lo:hi], fp_[lo:hi]))})
+    srv.close()
+    plain.close()
+    assert idx_b.info()["device_status"] == 0 and idx_p.info()["device_status"] == 0
+    top = rows[-1]
+    res = {
+        "value": top["continuous_batching"]["p99_ms"],
+        "ms_per_step": top["continuous_batching"]["mean_ms"],
+        "docs_timed": int(sum(r["docs"] for r in rows)),
+        "loads": rows,
+        "preload_docs": preload_n,
+        "preload_s": t_pre,
+        "filter_bytes": idx_b.info()["filter_bytes"],
+        "corpus_gen_s": t_gen,
+    }
+    idx_b.close()
+    idx_p.close()
+    return res, None, None
+
+
 DESCRIPTIONS = {
     "c2": "plain method on GPU: 1M-doc synthetic corpus (Zipf(1.1)/50k-vocab uint32 tokens, lognormal lengths "
           "median 3000 sigma 0.8 cap 50000, 20% near-dups J 0.6-0.95), 5-shingles, num_perm 128, 16 bands x 8 rows, "
@@ -248,6 +409,10 @@ DESCRIPTIONS = {
           "num_perm 256, 32 bands x 8 rows, filters n=100M fp=1e-8 (15.3 GB), batches of 1M",
     "c4": "filter-scale query-insert: 1B-signature stream of uniform uint32 (256 wide) with 30% one-band repeats, "
           "32 bands x 8 rows, filters n=1e9 fp=1e-10 per band (191.7 GB in HBM), batches of 1M (timed prefix)",
+    "c5": "serving: Poisson arrivals of 1-4096-document requests (log-uniform), lognormal lengths median 2000 "
+          "sigma 0.8, Zipf(1.1)/50k vocab, 15% near-dups of earlier served docs; filters preloaded with 1e8 "
+          "documents (num_perm 128, 16 bands x 8 rows, fp 1e-8 per band, 7.7 GB); continuous batching with "
+          "HBM-budget admission vs one request per batch",
 }
 
 
@@ -266,10 +431,20 @@ def main():
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
     wl = synth.WORKLOADS[args.workload]
+    higher = True
     if args.workload == "c4":
         res, corpus, idx = run_signatures(args, wl, torch, np, lshbloom, synth, dev)
         metric = "signatures/sec query-insert (band Bloom), bit-exact flags"
         unit = "sigs/s"
+    elif args.workload == "c5":
+        res, corpus, idx = run_serve(args, wl, torch, np, lshbloom, synth, dev)
+        metric = "p99 serve latency (ms) at the highest offered load, continuous batching"
+        unit = "ms"
+        higher = False
+    elif args.form == "batched":
+        res, corpus, idx = run_batched(args, wl, torch, np, lshbloom, synth, dev)
+        metric = "docs/sec end-to-end (MinHash+band Bloom), bit-exact flags"
+        unit = "docs/s"
     else:
         res, corpus, idx = run_corpus(args, wl, torch, np, lshbloom, synth, dev)
         metric = "docs/sec end-to-end (MinHash+band Bloom), bit-exact flags"
@@ -283,14 +458,14 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": res.pop("ms_per_step"),
-        "higher_is_better": True,
+        "higher_is_better": higher,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u32",
         "data": "synthetic",
         "config": {
             "workload": DESCRIPTIONS[args.workload],
-            "global_batch": wl.batch,
+            "global_batch": wl.batch if args.workload != "c5" else None,
             "docs_timed": res.pop("docs_timed"),
             "parallelism": "single-gpu",
         },

@@ -239,6 +239,10 @@ int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offse
 /* Block until the batch of `ticket` is done and its flags are in its h_flags. */
 int lshbloom_pipeline_wait(lshbloom_pipeline_t *pl, int64_t ticket);
 
+/* Non-blocking: 1 if the batch of `ticket` is done (its flags are then in
+ * its h_flags), 0 if not yet, negative on error. */
+int lshbloom_pipeline_poll(lshbloom_pipeline_t *pl, int64_t ticket);
+
 /* Chosen buckets, grid sizes and graph counters. */
 int lshbloom_pipeline_info(const lshbloom_pipeline_t *pl, lshbloom_pipeline_info_t *out);
 

@@ -500,6 +500,25 @@ int lshbloom_pipeline_wait(lshbloom_pipeline_t *pl, int64_t ticket) {
   return collect(S);
 }
 
+int lshbloom_pipeline_poll(lshbloom_pipeline_t *pl, int64_t ticket) {
+  if (!pl) {
+    set_err("pipeline_poll: null pipeline");
+    return LSHBLOOM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(pl->mu);
+  if (ticket < 0 || ticket >= pl->next_ticket) {
+    set_err("pipeline_poll: unknown ticket %lld", (long long)ticket);
+    return LSHBLOOM_EINVAL;
+  }
+  Slot &S = pl->slot[ticket % kSlots];
+  if (S.ticket != ticket || !S.pending) return 1;
+  const hipError_t q = hipEventQuery(S.done);
+  if (q == hipErrorNotReady) return 0;
+  if (q != hipSuccess) return fail_hip(nullptr, q, "pipeline_poll: event");
+  const int rc = collect(S);
+  return rc ? rc : 1;
+}
+
 int lshbloom_pipeline_info(const lshbloom_pipeline_t *plc, lshbloom_pipeline_info_t *out) {
   if (!plc || !out) {
     set_err("pipeline_info: null argument");

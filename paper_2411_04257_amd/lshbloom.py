@@ -98,8 +98,8 @@ EXPORTS = [
     "lshbloom_create", "lshbloom_create_ex", "lshbloom_destroy", "lshbloom_minhash", "lshbloom_query_insert",
     "lshbloom_query", "lshbloom_insert", "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters",
     "lshbloom_info", "lshbloom_p_band_from_eff", "lshbloom_optimal_bands", "lshbloom_last_error",
-    "lshbloom_pipeline_create", "lshbloom_pipeline_submit", "lshbloom_pipeline_wait", "lshbloom_pipeline_info",
-    "lshbloom_pipeline_destroy",
+    "lshbloom_pipeline_create", "lshbloom_pipeline_submit", "lshbloom_pipeline_wait", "lshbloom_pipeline_poll",
+    "lshbloom_pipeline_info", "lshbloom_pipeline_destroy",
 ]
 
 _lib = None
@@ -138,6 +138,8 @@ def load(path: str = LIB_PATH):
     L.lshbloom_pipeline_submit.restype = i64
     L.lshbloom_pipeline_wait.argtypes = [vp, i64]
     L.lshbloom_pipeline_wait.restype = ctypes.c_int
+    L.lshbloom_pipeline_poll.argtypes = [vp, i64]
+    L.lshbloom_pipeline_poll.restype = ctypes.c_int
     L.lshbloom_pipeline_info.argtypes = [vp, ctypes.POINTER(PipelineInfo)]
     L.lshbloom_pipeline_info.restype = ctypes.c_int
     L.lshbloom_pipeline_destroy.argtypes = [vp]
@@ -344,6 +346,15 @@ class Pipeline:
     def wait(self, ticket: int) -> None:
         _check(load().lshbloom_pipeline_wait(self._p, ticket))
         self._keep.pop(ticket, None)
+
+    def poll(self, ticket: int) -> bool:
+        """True once the batch is done (its flags are then in place)."""
+        rc = load().lshbloom_pipeline_poll(self._p, ticket)
+        if rc < 0:
+            raise LSHBloomError(rc, last_error())
+        if rc == 1:
+            self._keep.pop(ticket, None)
+        return rc == 1
 
     def info(self) -> dict:
         inf = PipelineInfo()
