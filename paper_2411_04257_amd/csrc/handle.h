@@ -29,11 +29,12 @@ struct lshbloom {
   // binned query-insert workspace
   uint32_t qi_mode = 0;
   uint64_t bin_chunk = 0;
-  uint64_t bin_counts_cap = 0;  // entries of counts1 / offs1
-  uint64_t bin_supers_cap = 0;
-  uint64_t bin_off2_cap = 0;
-  uint32_t *d_counts1 = nullptr, *d_offs1 = nullptr, *d_super = nullptr, *d_off2 = nullptr;
-  uint64_t *d_rec1 = nullptr, *d_rec2 = nullptr;
+  uint64_t bin_counts_cap = 0;  // entries of the pass-1 count/offset array
+  uint64_t bin_buckets_cap = 0; // bucket starts
+  uint64_t bin_bins_cap = 0;    // bin offsets / directory
+  uint32_t *d_counts1 = nullptr, *d_bstart = nullptr, *d_off2 = nullptr;
+  uint64_t *d_rec1 = nullptr, *d_rec2 = nullptr, *d_bkeys = nullptr, *d_dir = nullptr;
+  uint8_t *d_res0 = nullptr;
   int minhash_waves = 0;
   hipEvent_t last = nullptr;
   bool has_last = false;

@@ -87,11 +87,13 @@ void free_all(lshbloom *h) {
   if (h->d_hitb) (void)hipFree(h->d_hitb);
   if (h->d_status) (void)hipFree(h->d_status);
   if (h->d_counts1) (void)hipFree(h->d_counts1);
-  if (h->d_offs1) (void)hipFree(h->d_offs1);
-  if (h->d_super) (void)hipFree(h->d_super);
+  if (h->d_bstart) (void)hipFree(h->d_bstart);
   if (h->d_off2) (void)hipFree(h->d_off2);
+  if (h->d_dir) (void)hipFree(h->d_dir);
   if (h->d_rec1) (void)hipFree(h->d_rec1);
   if (h->d_rec2) (void)hipFree(h->d_rec2);
+  if (h->d_bkeys) (void)hipFree(h->d_bkeys);
+  if (h->d_res0) (void)hipFree(h->d_res0);
   if (h->last) (void)hipEventDestroy(h->last);
 }
 
@@ -187,26 +189,21 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
       a.salt1 = h->salt1;
       a.salt2 = h->salt2;
       a.filters = h->d_filters;
-      a.bin_bits = G.bin_bits;
-      a.bins_per_band = G.bins_per_band;
-      a.bins_per_super = G.bins_per_super;
-      a.supers_per_band = G.supers_per_band;
-      a.n_supers = G.n_supers;
-      a.items_per_block = G.items_per_block;
-      a.n_blocks1 = G.n_blocks1;
+      a.G = G;
       a.n_records = (uint32_t)((uint64_t)cn * pd);
-      a.counts1 = h->d_counts1;
-      a.offs1 = h->d_offs1;
-      a.super_tot = h->d_super;
+      a.keys = h->d_bkeys;
+      a.counts = h->d_counts1;
+      a.bstart = h->d_bstart;
       a.rec1 = h->d_rec1;
       a.rec2 = h->d_rec2;
-      a.table = h->d_rec1;
       a.off2 = h->d_off2;
-      a.hitb = h->d_hitb;
+      a.dir = h->d_dir;
+      a.res0 = h->d_res0;
       a.flags = d_flags + c0;
       a.status = h->d_status;
-      if ((uint64_t)G.n_supers > h->bin_supers_cap || (uint64_t)G.n_supers * G.n_blocks1 > h->bin_counts_cap ||
-          (uint64_t)h->prm.bands * G.bins_per_band + 1 > h->bin_off2_cap) {
+      if (lb::binned_counts_entries(G, h->prm.bands) > h->bin_counts_cap ||
+          lb::binned_bucket_entries(G, h->prm.bands) > h->bin_buckets_cap ||
+          lb::binned_bin_entries(G, h->prm.bands) > h->bin_bins_cap) {
         set_err("query_insert: binned geometry exceeds the workspace (internal error)");
         h->poisoned = true;
         return LSHBLOOM_EHIP;
@@ -367,8 +364,10 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   h->chunk_docs = chunk;
   h->table_slots_max = slots;
 
-  // Binned query-insert: 24 bytes per probe of a chunk (pass-1 records reused
-  // as the published tables, 2 x 8 B, plus the binned records, 8 B).
+  // Binned query-insert: 24 bytes per probe of a chunk (pass-1 records, 8 B,
+  // whose space then holds the published tables, 2 x 8 B per record, and the
+  // binned records, 8 B) plus 9 bytes per (document, band) (band keys and
+  // probe-0 answers) and the count, bucket and bin arrays.
   h->qi_mode = prm.qi_mode;
   if (const char *qm = std::getenv("LSHBLOOM_QI_MODE")) {
     if (!std::strcmp(qm, "direct")) h->qi_mode = 1;
@@ -377,20 +376,21 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   uint64_t bin_chunk = 0, bin_ws = 0;
   if (h->qi_mode != 1) {
     const uint64_t budget = prm.workspace_budget ? prm.workspace_budget : (4ull << 30);
-    bin_chunk = prm.chunk_docs ? prm.chunk_docs : budget / (24 * probes_per_doc);
+    const uint64_t per_doc = 24 * probes_per_doc + 9ull * prm.bands;
+    bin_chunk = prm.chunk_docs ? prm.chunk_docs : budget / per_doc;
     if (!prm.chunk_docs) bin_chunk = std::min<uint64_t>(bin_chunk, std::max<uint64_t>(prm.expected_n, 65536));
-    bin_chunk = std::min<uint64_t>(bin_chunk, (1ull << 24) - 1);                 // document index field
-    bin_chunk = std::min<uint64_t>(bin_chunk, 0xFFFFFFFFull / probes_per_doc);   // 32-bit record offsets
+    bin_chunk = std::min<uint64_t>(bin_chunk, lb::kBinnedMaxDocs);                       // document field
+    bin_chunk = std::min<uint64_t>(bin_chunk, lb::kBinnedMaxRecords / probes_per_doc);   // record offsets
     if (bin_chunk < 1) bin_chunk = 1;
-    const lb::BinnedGeometry g_big = lb::binned_geometry(bin_chunk, prm.bands, k, h->m_bits);
-    const lb::BinnedGeometry g_small = lb::binned_geometry(1, prm.bands, k, h->m_bits);
-    h->bin_supers_cap = std::max<uint64_t>(std::max(g_big.n_supers, g_small.n_supers), 1);
-    h->bin_counts_cap = h->bin_supers_cap * 1536;
-    h->bin_off2_cap = std::max(g_big.bins_per_band, g_small.bins_per_band) * prm.bands + 1;
-    bin_ws = bin_chunk * probes_per_doc * 24 + h->bin_counts_cap * 8 + h->bin_supers_cap * 4 + h->bin_off2_cap * 4;
+    // the arrays grow with the chunk (fewer records per band mean wider bins)
+    const lb::BinnedGeometry g = lb::binned_geometry(bin_chunk, prm.bands, k, h->m_bits);
+    h->bin_counts_cap = lb::binned_counts_entries(g, prm.bands);
+    h->bin_buckets_cap = lb::binned_bucket_entries(g, prm.bands);
+    h->bin_bins_cap = lb::binned_bin_entries(g, prm.bands);
+    bin_ws = bin_chunk * per_doc + h->bin_counts_cap * 4 + h->bin_buckets_cap * 4 + h->bin_bins_cap * 12;
   }
   h->bin_chunk = bin_chunk;
-  const uint64_t hitb_docs = std::max(chunk, bin_chunk);
+  const uint64_t hitb_docs = chunk;
 
   const uint64_t filter_bytes = h->m_bits / 8 * prm.bands;
   const uint64_t ws = slots * 8 + chunk * prm.bands * (8 + 8) + hitb_docs * prm.bands +
@@ -439,11 +439,13 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   LB_ALLOC(h->d_hitb, hitb_docs * prm.bands);
   if (bin_chunk) {
     LB_ALLOC(h->d_counts1, h->bin_counts_cap * 4);
-    LB_ALLOC(h->d_offs1, h->bin_counts_cap * 4);
-    LB_ALLOC(h->d_super, h->bin_supers_cap * 4);
-    LB_ALLOC(h->d_off2, h->bin_off2_cap * 4);
+    LB_ALLOC(h->d_bstart, h->bin_buckets_cap * 4);
+    LB_ALLOC(h->d_off2, h->bin_bins_cap * 4);
+    LB_ALLOC(h->d_dir, h->bin_bins_cap * 8);
     LB_ALLOC(h->d_rec1, bin_chunk * probes_per_doc * 16);
     LB_ALLOC(h->d_rec2, bin_chunk * probes_per_doc * 8);
+    LB_ALLOC(h->d_bkeys, bin_chunk * prm.bands * 8);
+    LB_ALLOC(h->d_res0, bin_chunk * prm.bands);
   }
   LB_ALLOC(h->d_coef, prm.num_perm * sizeof(lb::PermCoef));
   LB_ALLOC(h->d_status, 256);

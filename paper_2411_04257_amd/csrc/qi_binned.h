@@ -6,16 +6,27 @@
 
 namespace lb {
 
-// Bin geometry of one chunk: bins of 2^bin_bits bits within a band, grouped
-// into super bins of bins_per_super consecutive bins of one band.
+// Documents per pass-1 block (a power of two: a block's probe slots are
+// enumerated l-major, slot = l * kTileDocs + document).
+constexpr uint32_t kTileDocs = 1024;
+constexpr uint32_t kTileLog = 10;
+// Largest chunk the 64-bit record format holds: document index in 23 bits.
+constexpr uint64_t kBinnedMaxDocs = (1ull << 23) - 1;
+// Records per chunk must stay below 2^31 (32-bit record offsets and table caps).
+constexpr uint64_t kBinnedMaxRecords = (1ull << 31) - 1;
+
+// Bin geometry of one chunk.  Bits of band j are cut into bins of 2^bin_bits
+// bits (one workgroup owns a bin); bins are grouped into buckets of
+// bins_per_bucket consecutive bins (2^bucket_bits bits), the unit of the
+// first partition pass.
 struct BinnedGeometry {
   uint32_t bin_bits;
   uint64_t bins_per_band;
-  uint32_t bins_per_super;
-  uint32_t supers_per_band;
-  uint32_t n_supers;
-  uint32_t items_per_block;  // (document, band) items per pass-1 block
-  uint32_t n_blocks1;
+  uint32_t bucket_bits;
+  uint32_t buckets_per_band;  // F1: fan-out of pass 1 within a band
+  uint32_t bins_per_bucket;   // F2: fan-out of pass 2
+  uint32_t n_tiles;           // pass-1 blocks per band
+  bool direct_words;          // a bin's filter words fit in LDS (bin_bits <= 15)
 };
 
 struct BinnedLaunch {
@@ -25,30 +36,36 @@ struct BinnedLaunch {
   uint64_t m_bits, words_per_band;
   uint64_t salt_m, salt1, salt2;
   uint64_t *filters;
-  // geometry
-  uint32_t bin_bits;
-  uint64_t bins_per_band;
-  uint32_t bins_per_super, supers_per_band, n_supers;
-  uint32_t items_per_block, n_blocks1;
-  uint32_t n_records;  // n * bands * k (< 2^32)
+  BinnedGeometry G;
+  uint32_t n_records;  // n * bands * k (< 2^31)
   // workspace
-  uint32_t *counts1;  // [n_supers][n_blocks1]
-  uint32_t *offs1;    // [n_supers][n_blocks1] absolute record offsets
-  uint32_t *super_tot;  // [n_supers] records per super bin, then their starts
-  uint64_t *rec1;     // pass-1 records; reused as the published bit tables (2 slots per record)
-  uint64_t *rec2;     // records grouped by bin
-  uint64_t *table;    // == rec1
-  uint32_t *off2;     // [bands * bins_per_band + 1] record offsets of every bin
-  uint8_t *hitb;      // [n][bands]
-  uint8_t *flags;     // [n]
+  uint64_t *keys;      // [bands][n] band keys
+  uint32_t *counts;    // [bands][F1][n_tiles] per-block bucket counts, then offsets
+  uint32_t *bstart;    // [bands * F1 + 1] bucket totals, then starts
+  uint64_t *rec1;      // pass-1 records (bucket order); then the published tables (2 slots per record)
+  uint64_t *rec2;      // records in bin order
+  uint32_t *off2;      // [bands * bins_per_band + 1] first record of every bin
+  uint64_t *dir;       // [bands * bins_per_band] published table of a bin: first record << 32 | slots
+  uint8_t *res0;       // [bands][n] probe 0 of (document, band) was set before the document
+  uint8_t *flags;      // [n]
   uint32_t *status;
 };
 
-// Records per bin aimed at (the LDS path handles up to 1024).
-constexpr uint32_t kBinTarget = 512;
+// Records per bin aimed at (a bin's wave holds up to 320 in LDS).
+constexpr uint32_t kBinTarget = 192;
 
 BinnedGeometry binned_geometry(uint64_t n_docs, uint32_t bands, uint32_t k, uint64_t m_bits,
                                uint32_t target_per_bin = kBinTarget);
+// Workspace entries of a geometry (for sizing and checks).
+inline uint64_t binned_counts_entries(const BinnedGeometry &G, uint32_t bands) {
+  return (uint64_t)bands * G.buckets_per_band * G.n_tiles;
+}
+inline uint64_t binned_bucket_entries(const BinnedGeometry &G, uint32_t bands) {
+  return (uint64_t)bands * G.buckets_per_band + 1;
+}
+inline uint64_t binned_bin_entries(const BinnedGeometry &G, uint32_t bands) {
+  return (uint64_t)bands * G.bins_per_band + 1;
+}
 hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s);
 
 }  // namespace lb

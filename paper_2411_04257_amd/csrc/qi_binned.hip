@@ -1,33 +1,39 @@
-// Binned, atomic-free (on global memory) in-order query-insert for large
-// batches (Sections 2.1, 2.4, 4.1, 4.2, 4.4.2).
+// Binned in-order query-insert for large batches (Sections 2.1, 2.4, 4.1,
+// 4.2, 4.4.2), atomic-free on the filters.
 //
-// The direct query-insert of kernels.hip spends one device-scope atomic per
-// probe on the first-setter table and another on the filter word; on MI355X
-// those run near 2e10/s whatever the locality.  Here one chunk's probes are
-// partitioned by (band, bit range) so that one workgroup owns every probe of
-// a bin of 2^s filter bits:
+// A chunk's probes are partitioned by (band, bit range) so that one
+// workgroup owns every probe of a bin of 2^s filter bits and can settle the
+// in-chunk order of its bits in LDS:
 //
-//   pass 1 (k_bq_count1 / scan / k_bq_scatter1): per (document, band) item,
-//       the k Bloom positions, bucketed into "super bins" (ranges of bins of
-//       one band) with per-block LDS histograms, written as 64-bit records
-//       (document index << 40 | bit position);
-//   pass 2 (k_bq_part2): one block per super bin splits its records into bins
-//       and writes every bin's record range;
-//   bin   (k_bq_bin): one workgroup per bin reads the filter word of every
-//       record (the state before the chunk), builds in LDS a table of the
-//       bin's distinct bits with their first setter (minimum document index,
-//       or a marker when the bit was already set) and a table of OR masks per
-//       word, then writes the changed words back with plain stores (it is the
-//       only writer of its bit range) and publishes its bit table to global
-//       memory, in the same slot layout;
-//   resolve (k_bq_resolve): one thread per (document, band) looks its
-//       positions up in the published tables: a bit was set before document i
-//       iff it was set before the chunk or its first setter is < i; the band
-//       hits iff all k were, and the scan stops at the first miss.
+//   keys      (k_bq_keys): band key of every (document, band), band-major;
+//   pass 1    (k_bq_pass1<false>, scans, k_bq_pass1<true>): one block per
+//             (band, tile of 1024 documents) computes the k positions of its
+//             documents and writes 64-bit records
+//                 [probe-0 flag : 1][document : 23][bit position : 40]
+//             into buckets of consecutive bins, staging each 4096-record
+//             sub-tile in LDS so that every bucket's records leave as one
+//             contiguous run;
+//   pass 2    (k_bq_part2): one block per bucket counts its bins, publishes
+//             their record ranges and splits the bucket the same way;
+//   bins      (k_bq_bin): one workgroup per bin reads the bin's filter words
+//             (the state before the chunk), builds in LDS a table of its
+//             distinct bits with the least and greatest document probing
+//             each, ORs every probe into the words and writes the changed
+//             words back with plain stores (it is their only writer).  A bit
+//             was set before document i iff it was set before the chunk or
+//             its least document is < i.  The bin answers that at once for
+//             the probe-0 records (res0), and publishes the bits a later
+//             lookup can need: those set before the chunk and those probed
+//             by more than one document.  A bit probed by one document only
+//             was never set before that document, and no other document
+//             looks it up;
+//   resolve   (k_bq_resolve): per document and band, probe 0's answer
+//             decides most pairs (a miss ends the band); otherwise probes
+//             1..k-1 are looked up in the published tables with early exit.
 //
 // Every step is exact, so flags and final filter words equal the sequential
-// definition for every chunking; bins whose record count exceeds the LDS
-// capacity take a slower path with global-memory tables owned by the bin.
+// definition for every chunking.  Bins with more records than the LDS
+// tables hold take a slower path with their table in global memory.
 #include <hip/hip_runtime.h>
 
 #include "device_math.h"
@@ -37,9 +43,19 @@ namespace lb {
 
 namespace {
 
-constexpr uint32_t kInit = 0xFFFFFFFFu;   // bit set before the chunk
-constexpr uint32_t kNoFs = 0xFFFFFFFEu;   // no setter recorded yet
+constexpr uint32_t kThreads = 256;
+constexpr uint32_t kSub = 4096;               // records staged per sub-tile
+constexpr uint32_t kPer = kSub / kThreads;    // records per thread per sub-tile
+constexpr uint32_t kInit = 0xFFFFFFFFu;       // bit set before the chunk
+constexpr uint32_t kNoFs = 0xFFFFFFFEu;       // no document recorded yet
 constexpr uint64_t kMask40 = (1ull << 40) - 1;
+constexpr uint32_t kDocMask = (1u << 23) - 1;
+constexpr uint64_t kProbe0 = 1ull << 63;
+constexpr uint32_t kMaxF1 = 2048;
+constexpr uint32_t kKeysLds = 8192;           // signature words staged per keys block
+
+__host__ __device__ inline uint32_t keys_tile_docs(uint32_t br) { return br >= kKeysLds ? 1u : kKeysLds / br; }
+constexpr uint32_t kMaxF2 = 1024;
 
 // Slot of a 32-bit key in a table of `cap` slots (multiply-high range reduction).
 __device__ __forceinline__ uint32_t slot_of(uint32_t key, uint32_t cap) {
@@ -48,335 +64,590 @@ __device__ __forceinline__ uint32_t slot_of(uint32_t key, uint32_t cap) {
   return (uint32_t)(((uint64_t)(h2 ^ (h2 >> 13)) * cap) >> 32);
 }
 
-struct ItemPos {
-  uint64_t h1, h2;
-};
-
-__device__ __forceinline__ ItemPos item_hashes(const BinnedLaunch &A, int64_t i, uint32_t j) {
-  const uint64_t K = band_key(A.sigs + i * (int64_t)A.num_perm + (int64_t)j * A.rows, A.rows, A.salt_m);
-  return {fmix64(K ^ A.salt1), fmix64(K ^ A.salt2) | 1ull};
+// Exclusive scan of in[0..n) into out[0..n) (may alias) by a 256-thread
+// block of NT threads: each thread sums a run of consecutive entries, the
+// runs are scanned within each wave by shuffles and across the waves through
+// part[] (NT / 64 words of LDS).  Returns the total.  Every thread of the block must call
+// it; it ends with a barrier.
+template <uint32_t NT = kThreads>
+__device__ uint32_t block_scan(const uint32_t *in, uint32_t *out, uint32_t n, uint32_t *part) {
+  const uint32_t per = (n + NT - 1) / NT;
+  const uint32_t a = min(n, threadIdx.x * per), b = min(n, a + per);
+  const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  uint32_t s = 0;
+  for (uint32_t q = a; q < b; ++q) s += in[q];
+  uint32_t x = s;
+#pragma unroll
+  for (uint32_t off = 1; off < 64; off <<= 1) {
+    const uint32_t y = __shfl_up(x, off, 64);
+    if (lane >= off) x += y;
+  }
+  if (lane == 63) part[wave] = x;
+  __syncthreads();
+  uint32_t base = 0, total = 0;
+#pragma unroll
+  for (uint32_t w = 0; w < NT / 64; ++w) {
+    const uint32_t t = part[w];
+    if (w < wave) base += t;
+    total += t;
+  }
+  uint32_t run = base + x - s;
+  for (uint32_t q = a; q < b; ++q) {
+    const uint32_t v = in[q];
+    out[q] = run;
+    run += v;
+  }
+  __syncthreads();
+  return total;
 }
 
-__device__ __forceinline__ uint32_t super_of(const BinnedLaunch &A, uint32_t j, uint64_t g) {
-  const uint64_t lbin = g >> A.bin_bits;
-  return j * A.supers_per_band + (uint32_t)(lbin / A.bins_per_super);
+// ------------------------------------------------------------------ keys ----
+// Band keys of a tile of documents: the tile's first b*r signature values per
+// document are staged in LDS (coalesced reads, rows padded by one word), then
+// every (band, document) key is written band-major.
+__global__ __launch_bounds__(256) void k_bq_keys(BinnedLaunch A) {
+  extern __shared__ uint32_t srow[];
+  const uint32_t br = A.bands * A.rows, stride = br + 1;
+  const uint32_t td = keys_tile_docs(br);
+  const int64_t d0 = (int64_t)blockIdx.x * td;
+  const uint32_t nd = (uint32_t)min((int64_t)td, A.n - d0);
+  const uint32_t nq = nd * br;
+  for (uint32_t q0 = 0; q0 < nq; q0 += 8 * kThreads) {
+    uint32_t v[8];
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) {
+      const uint32_t q = q0 + u * kThreads + threadIdx.x;
+      const uint32_t d = q / br, c = q - d * br;
+      v[u] = q < nq ? A.sigs[(d0 + d) * (int64_t)A.num_perm + c] : 0u;
+    }
+#pragma unroll
+    for (uint32_t u = 0; u < 8; ++u) {
+      const uint32_t q = q0 + u * kThreads + threadIdx.x;
+      const uint32_t d = q / br, c = q - d * br;
+      if (q < nq) srow[d * stride + c] = v[u];
+    }
+  }
+  __syncthreads();
+  for (uint32_t p = threadIdx.x; p < nd * A.bands; p += kThreads) {
+    const uint32_t j = p / nd, d = p - j * nd;
+    A.keys[(int64_t)j * A.n + d0 + d] = band_key(&srow[d * stride + j * A.rows], A.rows, A.salt_m);
+  }
 }
 
 // ---------------------------------------------------------------- pass 1 ----
-__global__ __launch_bounds__(1024) void k_bq_count1(BinnedLaunch A) {
-  extern __shared__ uint32_t hist[];  // n_supers counters
-  for (uint32_t s = threadIdx.x; s < A.n_supers; s += blockDim.x) hist[s] = 0;
-  __syncthreads();
-  const int64_t items = A.n * (int64_t)A.bands;
-  const int64_t t0 = (int64_t)blockIdx.x * A.items_per_block;
-  const int64_t t1 = min(items, t0 + (int64_t)A.items_per_block);
-  for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-    const int64_t i = t / A.bands;
-    const uint32_t j = (uint32_t)(t - i * A.bands);
-    const ItemPos hp = item_hashes(A, i, j);
-    for (uint32_t l = 0; l < A.k; ++l) {
-      const uint64_t g = umulhi64(hp.h1 + (uint64_t)l * hp.h2, A.m_bits);
-      atomicAdd(&hist[super_of(A, j, g)], 1u);
-    }
+// Block (tile, band j).  COUNT: per-bucket record counts of the block.
+// SCATTER: the records, written to counts-derived offsets.
+template <bool SCATTER>
+__global__ __launch_bounds__(256) void k_bq_pass1(BinnedLaunch A) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const BinnedGeometry &G = A.G;
+  const uint32_t F1 = G.buckets_per_band;
+  const uint32_t F1r = (F1 + 3) & ~3u;
+  uint64_t *h1 = (uint64_t *)smem;                  // [kTileDocs]
+  uint64_t *h2 = h1 + kTileDocs;                    // [kTileDocs]
+  uint64_t *stage = h2 + kTileDocs;                 // [kSub]
+  uint32_t *part = (uint32_t *)(stage + kSub);      // [256]
+  uint32_t *hist = part + kThreads;                 // [F1]
+  uint32_t *lstart = hist + F1r;                    // [F1]
+  uint32_t *cur = lstart + F1r;                     // [F1]
+  uint16_t *sb = (uint16_t *)(cur + F1r);           // [kSub]
+  const uint32_t j = blockIdx.y, tile = blockIdx.x;
+  const int64_t d0 = (int64_t)tile * kTileDocs;
+  const uint32_t nd = (uint32_t)min((int64_t)kTileDocs, A.n - d0);
+  const uint64_t *K = A.keys + (int64_t)j * A.n + d0;
+  for (uint32_t d = threadIdx.x; d < nd; d += kThreads) {
+    const uint64_t key = K[d];
+    h1[d] = fmix64(key ^ A.salt1);
+    h2[d] = fmix64(key ^ A.salt2) | 1ull;
+  }
+  const uint64_t row = ((uint64_t)j * F1) * G.n_tiles + tile;  // + f * n_tiles
+  for (uint32_t f = threadIdx.x; f < F1; f += kThreads) {
+    hist[f] = 0;
+    if (SCATTER) cur[f] = A.bstart[(uint64_t)j * F1 + f] + A.counts[row + (uint64_t)f * G.n_tiles];
   }
   __syncthreads();
-  for (uint32_t s = threadIdx.x; s < A.n_supers; s += blockDim.x)
-    A.counts1[(uint64_t)s * A.n_blocks1 + blockIdx.x] = hist[s];
-}
-
-__global__ __launch_bounds__(1024) void k_bq_scatter1(BinnedLaunch A) {
-  extern __shared__ uint32_t cur[];  // n_supers cursors
-  for (uint32_t s = threadIdx.x; s < A.n_supers; s += blockDim.x)
-    cur[s] = A.offs1[(uint64_t)s * A.n_blocks1 + blockIdx.x];
-  __syncthreads();
-  const int64_t items = A.n * (int64_t)A.bands;
-  const int64_t t0 = (int64_t)blockIdx.x * A.items_per_block;
-  const int64_t t1 = min(items, t0 + (int64_t)A.items_per_block);
-  for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
-    const int64_t i = t / A.bands;
-    const uint32_t j = (uint32_t)(t - i * A.bands);
-    const ItemPos hp = item_hashes(A, i, j);
-    for (uint32_t l = 0; l < A.k; ++l) {
-      const uint64_t g = umulhi64(hp.h1 + (uint64_t)l * hp.h2, A.m_bits);
-      const uint32_t pos = atomicAdd(&cur[super_of(A, j, g)], 1u);
-      A.rec1[pos] = ((uint64_t)i << 40) | g;
+  const uint32_t total = kTileDocs * A.k;
+  if (!SCATTER) {
+    for (uint32_t q = threadIdx.x; q < total; q += kThreads) {
+      const uint32_t d = q & (kTileDocs - 1), l = q >> kTileLog;
+      if (d >= nd) continue;
+      const uint64_t g = umulhi64(h1[d] + (uint64_t)l * h2[d], A.m_bits);
+      atomicAdd(&hist[(uint32_t)(g >> G.bucket_bits)], 1u);
     }
+    __syncthreads();
+    for (uint32_t f = threadIdx.x; f < F1; f += kThreads) A.counts[row + (uint64_t)f * G.n_tiles] = hist[f];
+    return;
   }
-}
-
-// Exclusive scan of every super bin's row of per-block counts (one block per
-// super bin); the row total goes to super_tot.
-__global__ __launch_bounds__(1024) void k_bq_rowscan(BinnedLaunch A) {
-  __shared__ uint32_t buf[1024];
-  __shared__ uint32_t carry;
-  const uint32_t s = blockIdx.x;
-  const uint32_t *in = A.counts1 + (uint64_t)s * A.n_blocks1;
-  uint32_t *out = A.offs1 + (uint64_t)s * A.n_blocks1;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t base = 0; base < A.n_blocks1; base += 1024) {
-    const uint32_t idx = base + threadIdx.x;
-    const uint32_t v = idx < A.n_blocks1 ? in[idx] : 0u;
-    buf[threadIdx.x] = v;
-    __syncthreads();
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-      const uint32_t add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0u;
-      __syncthreads();
-      buf[threadIdx.x] += add;
-      __syncthreads();
+  for (uint32_t q0 = 0; q0 < total; q0 += kSub) {
+    uint64_t rec[kPer];
+    uint32_t bk[kPer], rk[kPer];
+#pragma unroll
+    for (uint32_t u = 0; u < kPer; ++u) {
+      const uint32_t q = q0 + u * kThreads + threadIdx.x;
+      const uint32_t d = q & (kTileDocs - 1), l = q >> kTileLog;
+      bk[u] = 0xFFFFFFFFu;
+      if (q < total && d < nd) {
+        const uint64_t g = umulhi64(h1[d] + (uint64_t)l * h2[d], A.m_bits);
+        const uint32_t f = (uint32_t)(g >> G.bucket_bits);
+        bk[u] = f;
+        rk[u] = atomicAdd(&hist[f], 1u);
+        rec[u] = (l == 0 ? kProbe0 : 0ull) | ((uint64_t)(d0 + d) << 40) | g;
+      }
     }
-    const uint32_t incl = buf[threadIdx.x];
-    if (idx < A.n_blocks1) out[idx] = carry + incl - v;
     __syncthreads();
-    if (threadIdx.x == 1023) carry += incl;
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) A.super_tot[s] = carry;
-}
-
-// Exclusive scan of the super bins' totals (one block), then every row of
-// offs1 is shifted by its super bin's start (grid over rows).
-__global__ __launch_bounds__(1024) void k_bq_superscan(BinnedLaunch A) {
-  __shared__ uint32_t buf[1024];
-  __shared__ uint32_t carry;
-  if (threadIdx.x == 0) carry = 0;
-  __syncthreads();
-  for (uint32_t base = 0; base < A.n_supers; base += 1024) {
-    const uint32_t idx = base + threadIdx.x;
-    const uint32_t v = idx < A.n_supers ? A.super_tot[idx] : 0u;
-    buf[threadIdx.x] = v;
-    __syncthreads();
-    for (uint32_t off = 1; off < 1024; off <<= 1) {
-      const uint32_t add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0u;
-      __syncthreads();
-      buf[threadIdx.x] += add;
-      __syncthreads();
+    const uint32_t cnt = block_scan(hist, lstart, F1, part);
+#pragma unroll
+    for (uint32_t u = 0; u < kPer; ++u) {
+      if (bk[u] != 0xFFFFFFFFu) {
+        const uint32_t p = lstart[bk[u]] + rk[u];
+        stage[p] = rec[u];
+        sb[p] = (uint16_t)bk[u];
+      }
     }
-    const uint32_t incl = buf[threadIdx.x];
-    if (idx < A.n_supers) A.super_tot[idx] = carry + incl - v;  // now the super bin's start
     __syncthreads();
-    if (threadIdx.x == 1023) carry += incl;
+    for (uint32_t p = threadIdx.x; p < cnt; p += kThreads) {
+      const uint32_t f = sb[p];
+      A.rec1[cur[f] + (p - lstart[f])] = stage[p];
+    }
+    __syncthreads();
+    for (uint32_t f = threadIdx.x; f < F1; f += kThreads) {
+      cur[f] += hist[f];
+      hist[f] = 0;
+    }
     __syncthreads();
   }
 }
 
-__global__ __launch_bounds__(256) void k_bq_rowshift(BinnedLaunch A) {
-  const uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x;
-  if (q >= (uint64_t)A.n_supers * A.n_blocks1) return;
-  A.offs1[q] += A.super_tot[q / A.n_blocks1];
+// Exclusive scan of every (band, bucket) row of per-block counts; the row
+// total goes to bstart.
+__global__ __launch_bounds__(256) void k_bq_scan_tiles(BinnedLaunch A) {
+  __shared__ uint32_t part[kThreads];
+  uint32_t *row = A.counts + (uint64_t)blockIdx.x * A.G.n_tiles;
+  const uint32_t t = block_scan(row, row, A.G.n_tiles, part);
+  if (threadIdx.x == 0) A.bstart[blockIdx.x] = t;
+}
+
+// Exclusive scan of the bucket totals (one block): bucket starts, and the
+// record count at the end.
+__global__ __launch_bounds__(256) void k_bq_scan_buckets(BinnedLaunch A) {
+  __shared__ uint32_t part[kThreads];
+  const uint32_t nb = A.bands * A.G.buckets_per_band;
+  const uint32_t t = block_scan(A.bstart, A.bstart, nb, part);
+  if (threadIdx.x == 0) {
+    A.bstart[nb] = t;
+    if (t != A.n_records) atomicOr(A.status, 8u);
+  }
 }
 
 // ---------------------------------------------------------------- pass 2 ----
-// One block per super bin: count its records per bin, scan in LDS, publish
-// the bins' offsets and scatter the records by bin.
+// One 1024-thread block per bucket (one block fills a compute unit's LDS):
+// count its bins, publish their record ranges, and split the bucket into
+// bins through LDS-staged sub-tiles of 16,384 records, so that each bin's
+// share of a sub-tile leaves as one contiguous run.
+constexpr uint32_t kT2 = 1024;
+constexpr uint32_t kPer2 = 16;
+constexpr uint32_t kSub2 = kT2 * kPer2;
+
 __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
-  extern __shared__ uint32_t cnt[];  // bins_per_super counters
-  const uint32_t s = blockIdx.x;
-  const uint32_t j = s / A.supers_per_band;
-  const uint64_t first_lbin = (uint64_t)(s % A.supers_per_band) * A.bins_per_super;
-  const uint32_t r0 = A.super_tot[s];
-  const uint32_t r1 = (s + 1 < A.n_supers) ? A.super_tot[s + 1] : A.n_records;
-  const uint32_t fb = A.bins_per_super;
-  for (uint32_t f = threadIdx.x; f < fb; f += blockDim.x) cnt[f] = 0;
-  __syncthreads();
-  for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const uint64_t g = A.rec1[r] & kMask40;
-    atomicAdd(&cnt[(uint32_t)((g >> A.bin_bits) - first_lbin)], 1u);
+  extern __shared__ __align__(16) uint8_t smem[];
+  const BinnedGeometry &G = A.G;
+  const uint32_t F2 = G.bins_per_bucket;
+  uint64_t *stage = (uint64_t *)smem;            // [kSub2]
+  uint32_t *cur = (uint32_t *)(stage + kSub2);   // [F2]
+  uint32_t *h = cur + F2;                        // [F2]
+  uint32_t *lstart = h + F2;                     // [F2]
+  uint32_t *part = lstart + F2;                  // [16]
+
+  const uint32_t q = blockIdx.x;
+  const uint32_t j = q / G.buckets_per_band, f = q - j * G.buckets_per_band;
+  const uint32_t s0 = A.bstart[q], s1 = A.bstart[q + 1];
+  const uint64_t first_bin = (uint64_t)f * F2;  // within the band
+  const uint64_t nbins = min((uint64_t)F2, G.bins_per_band - first_bin);
+  for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
+    cur[b] = 0;
+    h[b] = 0;
   }
   __syncthreads();
-  // exclusive scan of cnt[0..fb) by thread 0..: fb <= 4096, simple strided
-  // two-level scan: each thread sums a run, then the runs are scanned.
-  __shared__ uint32_t run[1024];
-  const uint32_t per = (fb + blockDim.x - 1) / blockDim.x;
-  const uint32_t f0 = threadIdx.x * per, f1 = min(fb, f0 + per);
-  uint32_t sum = 0;
-  for (uint32_t f = f0; f < f1; ++f) sum += cnt[f];
-  run[threadIdx.x] = sum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t acc = 0;
-    for (uint32_t q = 0; q < blockDim.x; ++q) {
-      const uint32_t v = run[q];
-      run[q] = acc;
-      acc += v;
+  for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
+    uint64_t g[kPer2];
+#pragma unroll
+    for (uint32_t u = 0; u < kPer2; ++u) {
+      const uint32_t r = q0 + u * kT2 + threadIdx.x;
+      g[u] = r < s1 ? (A.rec1[r] & kMask40) : ~0ull;
     }
+#pragma unroll
+    for (uint32_t u = 0; u < kPer2; ++u)
+      if (g[u] != ~0ull) atomicAdd(&cur[(uint32_t)((g[u] >> G.bin_bits) - first_bin)], 1u);
   }
   __syncthreads();
-  uint32_t acc = r0 + run[threadIdx.x];
-  for (uint32_t f = f0; f < f1; ++f) {
-    const uint32_t v = cnt[f];
-    cnt[f] = acc;  // becomes the cursor
-    const uint64_t lbin = first_lbin + f;
-    if (lbin < A.bins_per_band) A.off2[(uint64_t)j * A.bins_per_band + lbin] = acc;
-    acc += v;
+  block_scan<kT2>(cur, cur, F2, part);
+  for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
+    cur[b] += s0;
+    if (b < nbins) A.off2[(uint64_t)j * G.bins_per_band + first_bin + b] = cur[b];
   }
+  if (q + 1 == A.bands * G.buckets_per_band && threadIdx.x == 0)
+    A.off2[(uint64_t)A.bands * G.bins_per_band] = A.n_records;
   __syncthreads();
-  for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-    const uint64_t rec = A.rec1[r];
-    const uint64_t g = rec & kMask40;
-    const uint32_t pos = atomicAdd(&cnt[(uint32_t)((g >> A.bin_bits) - first_lbin)], 1u);
-    A.rec2[pos] = rec;
+  for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
+    uint64_t rec[kPer2];
+    uint32_t rk[kPer2];
+#pragma unroll
+    for (uint32_t u = 0; u < kPer2; ++u) {
+      const uint32_t r = q0 + u * kT2 + threadIdx.x;
+      rec[u] = r < s1 ? A.rec1[r] : ~0ull;
+      if (rec[u] != ~0ull) rk[u] = atomicAdd(&h[(uint32_t)(((rec[u] & kMask40) >> G.bin_bits) - first_bin)], 1u);
+    }
+    __syncthreads();
+    const uint32_t cnt = block_scan<kT2>(h, lstart, F2, part);
+#pragma unroll
+    for (uint32_t u = 0; u < kPer2; ++u)
+      if (rec[u] != ~0ull) stage[lstart[(uint32_t)(((rec[u] & kMask40) >> G.bin_bits) - first_bin)] + rk[u]] = rec[u];
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < cnt; p += kT2) {
+      const uint64_t r = stage[p];
+      const uint32_t b = (uint32_t)(((r & kMask40) >> G.bin_bits) - first_bin);
+      A.rec2[cur[b] + (p - lstart[b])] = r;
+    }
+    __syncthreads();
+    for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
+      cur[b] += h[b];
+      h[b] = 0;
+    }
+    __syncthreads();
   }
-  if (s == A.n_supers - 1 && threadIdx.x == 0) A.off2[(uint64_t)A.bands * A.bins_per_band] = A.n_records;
 }
 
 // ------------------------------------------------------------------- bins ----
-constexpr uint32_t kBinCap = 1024;       // records per bin handled in LDS
-constexpr uint32_t kTab = 2 * kBinCap;   // LDS table slots
+// One wave per bin (64-thread workgroups), so that a bin's steps need no
+// workgroup barrier and several bins per SIMD overlap their memory latency.
+// LDS holds, per wave, the bin's distinct bits (key = local bit + 1, bit 31
+// marking "probed by two documents or more") with their least document, and
+// either the bin's filter words (direct mode) or a table of the words it
+// touches with their OR masks; that space then holds the published table.
+constexpr uint32_t kWCap = 320;               // records per bin on the wave path
+constexpr uint32_t kWPer = kWCap / 64;        // records per lane
+constexpr uint32_t kWTab = 2 * kWCap;         // bit / word table slots
+constexpr uint32_t kWRegion = 512;            // direct mode: the bin's words (bin_bits <= 15)
+constexpr uint32_t kMulti = 0x80000000u;
 
-__global__ __launch_bounds__(256) void k_bq_bin(BinnedLaunch A) {
-  __shared__ uint32_t tkey[kTab];  // bit table: local bit + 1 (0 = empty)
-  __shared__ uint32_t tval[kTab];  // first setter, or kInit
-  __shared__ uint32_t wkey[kTab];  // word table: local word + 1
-  __shared__ unsigned long long wmask[kTab];
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
-  const uint64_t n_bins = (uint64_t)A.bands * A.bins_per_band;
-  for (uint64_t bin = blockIdx.x; bin < n_bins; bin += gridDim.x) {
-    const uint32_t r0 = A.off2[bin], r1 = A.off2[bin + 1];
-    const uint32_t nr = r1 - r0;
-    if (nr == 0) continue;
-    const uint32_t j = (uint32_t)(bin / A.bins_per_band);
-    const uint64_t lbin = bin - (uint64_t)j * A.bins_per_band;
-    const uint64_t b0 = lbin << A.bin_bits;  // first bit of the bin (multiple of 64)
-    uint64_t *F = A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6);
-    uint64_t *T = A.table + 2ull * r0;
-    const uint32_t cap = 2 * nr;
-    if (nr <= kBinCap) {
-      for (uint32_t q = threadIdx.x; q < cap; q += blockDim.x) {
-        tkey[q] = 0;
-        tval[q] = kNoFs;
-        wkey[q] = 0;
-        wmask[q] = 0;
-      }
-      __syncthreads();
-      for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const uint64_t rec = A.rec2[r];
-        const uint32_t i = (uint32_t)(rec >> 40);
-        const uint32_t lb = (uint32_t)((rec & kMask40) - b0);
-        const uint32_t lw = lb >> 6;
-        const bool init = (F[lw] >> (lb & 63)) & 1ull;
-        uint32_t h = slot_of(lb, cap);
-        for (uint32_t tries = 0; tries < cap; ++tries) {
-          const uint32_t old = atomicCAS(&tkey[h], 0u, lb + 1);
-          if (old == 0u || old == lb + 1) break;
-          h = (h + 1 == cap) ? 0 : h + 1;
+__device__ __forceinline__ uint32_t lds_insert(uint32_t *keys, uint32_t key1, uint32_t cap, uint32_t *status) {
+  uint32_t h = slot_of(key1 - 1, cap);
+  for (uint32_t tries = 0; tries < cap; ++tries) {
+    const uint32_t old = atomicCAS(&keys[h], 0u, key1);
+    if (old == 0u || (old & ~kMulti) == key1) return h;
+    h = (h + 1 == cap) ? 0 : h + 1;
+  }
+  atomicOr(status, 4u);  // cannot happen: cap >= 2 x distinct keys
+  return 0;
+}
+
+// A bin with more records than the wave's LDS tables hold: its table (every
+// distinct bit, 2 slots per record) is built in the bin's own slots of the
+// table area with device atomics; filter bits are set after every record has
+// read the state before the chunk.
+__device__ void bin_global(const BinnedLaunch &A, uint32_t j, uint64_t bin, uint32_t r0, uint32_t r1, uint64_t b0,
+                           uint64_t *F) {
+  const uint32_t lane = threadIdx.x;
+  const uint32_t nr = r1 - r0, cap = 2 * nr;
+  unsigned long long *T = (unsigned long long *)(A.rec1 + 2ull * r0);
+  for (uint32_t q = lane; q < cap; q += 64) T[q] = (unsigned long long)kNoFs;
+  __threadfence();
+  wave_sync();
+  for (uint32_t r = r0 + lane; r < r1; r += 64) {
+    const uint64_t rec = A.rec2[r];
+    const uint32_t i = (uint32_t)(rec >> 40) & kDocMask;
+    const uint32_t lb = (uint32_t)((rec & kMask40) - b0);
+    const bool init = (F[lb >> 6] >> (lb & 63)) & 1ull;
+    uint32_t h = slot_of(lb, cap);
+    bool placed = false;
+    for (uint32_t tries = 0; tries < cap && !placed;) {
+      unsigned long long cur = __hip_atomic_load(&T[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (;;) {
+        const uint32_t key = (uint32_t)(cur >> 32);
+        if (key == lb + 1) {
+          placed = true;
+          break;
         }
-        if (init)
-          tval[h] = kInit;
-        else
-          atomicMin(&tval[h], i);
+        if (key != 0) break;
+        const unsigned long long want = ((unsigned long long)(lb + 1) << 32) | kNoFs;
+        const unsigned long long old = atomicCAS(&T[h], cur, want);
+        if (old == cur) {
+          placed = true;
+          break;
+        }
+        cur = old;
+      }
+      if (!placed) {
+        h = (h + 1 == cap) ? 0 : h + 1;
+        ++tries;
+      }
+    }
+    if (!placed) {
+      atomicOr(A.status, 4u);
+      continue;
+    }
+    if (init)
+      atomicOr(&T[h], (unsigned long long)kInit);
+    else
+      atomicMin(&T[h], ((unsigned long long)(lb + 1) << 32) | i);
+  }
+  __threadfence();
+  wave_sync();
+  for (uint32_t r = r0 + lane; r < r1; r += 64) {
+    const uint64_t rec = A.rec2[r];
+    const uint32_t lb = (uint32_t)((rec & kMask40) - b0);
+    atomicOr((unsigned long long *)&F[lb >> 6], (unsigned long long)(1ull << (lb & 63)));
+    if (rec & kProbe0) {
+      const uint32_t i = (uint32_t)(rec >> 40) & kDocMask;
+      uint32_t h = slot_of(lb, cap);
+      uint32_t v = kNoFs;
+      for (uint32_t tries = 0; tries < cap; ++tries) {
+        const unsigned long long e = __hip_atomic_load(&T[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((uint32_t)(e >> 32) == lb + 1) {
+          v = (uint32_t)e;
+          break;
+        }
+        h = (h + 1 == cap) ? 0 : h + 1;
+      }
+      A.res0[(int64_t)j * A.n + i] = (v == kInit || v < i) ? 1 : 0;
+    }
+  }
+  if (lane == 0) A.dir[bin] = ((uint64_t)r0 << 32) | cap;
+  __threadfence();
+  wave_sync();
+}
+
+template <bool DIRECT>
+__global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
+  __shared__ uint32_t tkey[kWTab];
+  __shared__ uint32_t tmin[kWTab];  // least document probing the bit, or kInit
+  __shared__ unsigned long long wv[DIRECT ? kWRegion : kWTab];
+  __shared__ uint32_t wk[DIRECT ? kWRegion / 32 : kWTab];  // direct: changed-word bits; else word keys
+
+  const uint32_t lane = threadIdx.x;
+  const BinnedGeometry &G = A.G;
+  const uint64_t n_bins = (uint64_t)A.bands * G.bins_per_band;
+  // The records of the wave's next bin are loaded while it works on the
+  // current one (records of bins above kWCap are not: bin_global reads them).
+  auto load_recs = [&](uint64_t b, uint32_t &q0, uint32_t &q1, uint64_t *out) {
+    q0 = q1 = 0;
+    if (b < n_bins) {
+      q0 = A.off2[b];
+      q1 = A.off2[b + 1];
+    }
+    const bool small = q1 - q0 <= kWCap;
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      const uint32_t r = q0 + u * 64 + lane;
+      out[u] = (small && r < q1) ? A.rec2[r] : ~0ull;
+    }
+  };
+  uint32_t r0, r1;
+  uint64_t rec[kWPer];
+  load_recs(blockIdx.x, r0, r1, rec);
+  for (uint64_t bin = blockIdx.x; bin < n_bins; bin += gridDim.x) {
+    const uint64_t nbin = bin + gridDim.x;
+    uint32_t q0, q1;
+    uint64_t nrec[kWPer];
+    const uint32_t nr = r1 - r0;
+    if (nr == 0 || nr > kWCap) {
+      if (nr > kWCap) {
+        const uint32_t j = (uint32_t)(bin / G.bins_per_band);
+        const uint64_t b0 = (bin - (uint64_t)j * G.bins_per_band) << G.bin_bits;
+        bin_global(A, j, bin, r0, r1, b0, A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6));
+      }
+      load_recs(nbin, q0, q1, nrec);
+      r0 = q0;
+      r1 = q1;
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
+      continue;
+    }
+    const uint32_t j = (uint32_t)(bin / G.bins_per_band);
+    const uint64_t lbin = bin - (uint64_t)j * G.bins_per_band;
+    const uint64_t b0 = lbin << G.bin_bits;  // first bit of the bin (a multiple of 64)
+    uint64_t *F = A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6);
+    const uint32_t cap = 2 * nr;
+    const uint32_t W = (uint32_t)min((uint64_t)1 << (G.bin_bits - 6), A.words_per_band - (b0 >> 6));
+    // this bin's loads first: its words (direct) or each record's word; then
+    // the next bin's records
+    for (uint32_t q = lane; q < cap; q += 64) {
+      tkey[q] = 0;
+      tmin[q] = kNoFs;
+      if (!DIRECT) {
+        wk[q] = 0;
+        wv[q] = 0;
+      }
+    }
+    if (DIRECT) {
+      uint64_t reg[kWRegion / 64];
+#pragma unroll
+      for (uint32_t u = 0; u < kWRegion / 64; ++u) {
+        const uint32_t w = u * 64 + lane;
+        reg[u] = w < W ? F[w] : 0ull;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kWRegion / 64; ++u) {
+        const uint32_t w = u * 64 + lane;
+        if (w < W) wv[w] = reg[u];
+      }
+      if (lane < kWRegion / 32) wk[lane] = 0;
+    }
+    uint64_t pre[DIRECT ? 1 : kWPer];
+    if (!DIRECT) {
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u)
+        pre[u] = rec[u] != ~0ull ? F[(uint32_t)((rec[u] & kMask40) - b0) >> 6] : 0ull;
+    }
+    load_recs(nbin, q0, q1, nrec);
+    wave_sync();
+    // phase A: state before the chunk, bit table, least document
+    uint32_t slot[kWPer];
+    uint32_t clear = 0;  // records whose bit was clear before the chunk
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      slot[u] = 0;
+      if (rec[u] == ~0ull) continue;
+      const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
+      const uint32_t lb = (uint32_t)((rec[u] & kMask40) - b0);
+      const uint64_t bit = 1ull << (lb & 63);
+      const bool init = ((DIRECT ? wv[lb >> 6] : pre[u]) & bit) != 0;
+      const uint32_t h = lds_insert(tkey, lb + 1, cap, A.status);
+      slot[u] = h;
+      if (init) {
+        tmin[h] = kInit;  // every record of this bit sees the same state
+      } else {
+        clear |= 1u << u;
+        const uint32_t old = atomicMin(&tmin[h], i);
+        if (old != kNoFs && old != i) atomicOr(&tkey[h], kMulti);
+      }
+    }
+    wave_sync();
+    // phase B: OR the newly set bits into the words
+    uint32_t owner = 0, wslot[DIRECT ? 1 : kWPer];
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      if (!(clear >> u & 1u)) continue;
+      const uint32_t lb = (uint32_t)((rec[u] & kMask40) - b0);
+      const uint32_t lw = lb >> 6;
+      const unsigned long long bit = 1ull << (lb & 63);
+      if (DIRECT) {
+        atomicOr(&wv[lw], bit);
+        atomicOr(&wk[lw >> 5], 1u << (lw & 31));
+      } else {
         uint32_t hw = slot_of(lw, cap);
         for (uint32_t tries = 0; tries < cap; ++tries) {
-          const uint32_t old = atomicCAS(&wkey[hw], 0u, lw + 1);
-          if (old == 0u || old == lw + 1) break;
+          const uint32_t old = atomicCAS(&wk[hw], 0u, lw + 1);
+          if (old == 0u) {
+            owner |= 1u << u;  // this record writes the word back
+            wslot[u] = hw;
+            break;
+          }
+          if (old == lw + 1) break;
           hw = (hw + 1 == cap) ? 0 : hw + 1;
         }
-        atomicOr(&wmask[hw], 1ull << (lb & 63));
+        atomicOr(&wv[hw], bit);
       }
-      __syncthreads();
-      for (uint32_t q = threadIdx.x; q < cap; q += blockDim.x) {
-        const uint32_t wk = wkey[q];
-        if (wk) {
-          const uint64_t old = F[wk - 1];
-          const uint64_t nw = old | wmask[q];
-          if (nw != old) F[wk - 1] = nw;
-        }
-        const uint32_t key = tkey[q];
-        T[q] = key ? (((uint64_t)key << 32) | tval[q]) : 0ull;
-      }
-      __syncthreads();
-    } else {
-      // Hot bin (many documents sharing bits): the same steps with the bit
-      // table in the bin's own global segment; filter bits are set after every
-      // record has read the state before the chunk.
-      for (uint32_t q = threadIdx.x; q < cap; q += blockDim.x) T[q] = ((uint64_t)0 << 32) | kNoFs;
-      __syncthreads();
-      for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const uint64_t rec = A.rec2[r];
-        const uint32_t i = (uint32_t)(rec >> 40);
-        const uint32_t lb = (uint32_t)((rec & kMask40) - b0);
-        const bool init = (F[lb >> 6] >> (lb & 63)) & 1ull;
-        uint32_t h = slot_of(lb, cap);
-        for (uint32_t tries = 0; tries < 4 * cap; ++tries) {
-          unsigned long long *slot = (unsigned long long *)&T[h];
-          const unsigned long long cur = *slot;
-          const uint32_t key = (uint32_t)(cur >> 32);
-          if (key == lb + 1) break;
-          if (key == 0) {
-            const unsigned long long want = ((unsigned long long)(lb + 1) << 32) | kNoFs;
-            const unsigned long long old = atomicCAS(slot, cur, want);
-            if (old == cur || (uint32_t)(old >> 32) == lb + 1) break;
-            continue;  // another key took the slot: look at it again
-          }
-          h = (h + 1 == cap) ? 0 : h + 1;
-        }
-        unsigned long long *slot = (unsigned long long *)&T[h];
-        if (init)
-          atomicOr(slot, (unsigned long long)kInit);  // low word becomes all ones
-        else
-          atomicMin(slot, ((unsigned long long)(lb + 1) << 32) | i);
-      }
-      __syncthreads();
-      for (uint32_t r = r0 + threadIdx.x; r < r1; r += blockDim.x) {
-        const uint32_t lb = (uint32_t)((A.rec2[r] & kMask40) - b0);
-        atomicOr((unsigned long long *)&F[lb >> 6], (unsigned long long)(1ull << (lb & 63)));
-      }
-      __syncthreads();
-      // empty slots must read as key 0
-      for (uint32_t q = threadIdx.x; q < cap; q += blockDim.x)
-        if ((uint32_t)(T[q] >> 32) == 0) T[q] = 0;
-      __syncthreads();
     }
+    wave_sync();
+    // changed words (this wave is their only writer in the chunk)
+    if (DIRECT) {
+      for (uint32_t w = lane; w < W; w += 64)
+        if (wk[w >> 5] >> (w & 31) & 1u) F[w] = wv[w];
+    } else {
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u)
+        if (owner >> u & 1u) F[(uint32_t)((rec[u] & kMask40) - b0) >> 6] = pre[u] | wv[wslot[u]];
+    }
+    // probe 0 of every (document, band) is answered here
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      if (rec[u] != ~0ull && (rec[u] & kProbe0)) {
+        const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
+        const uint32_t v = tmin[slot[u]];
+        A.res0[(int64_t)j * A.n + i] = (v == kInit || v < i) ? 1 : 0;
+      }
+    }
+    // publish the bits a lookup can need (set before the chunk, or probed by
+    // two documents or more)
+    uint32_t mine = 0;
+    for (uint32_t q = lane; q < cap; q += 64)
+      if (tkey[q] && (tmin[q] == kInit || (tkey[q] & kMulti))) ++mine;
+#pragma unroll
+    for (uint32_t off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
+    const uint32_t room = DIRECT ? kWRegion : kWTab;
+    const uint32_t pcap = min(2 * mine, room);
+    wave_sync();
+    for (uint32_t q = lane; q < pcap; q += 64) wv[q] = 0;
+    wave_sync();
+    for (uint32_t q = lane; q < cap; q += 64) {
+      const uint32_t key = tkey[q];
+      if (key && (tmin[q] == kInit || (key & kMulti))) {
+        const uint32_t k1 = key & ~kMulti;
+        uint32_t h = slot_of(k1 - 1, pcap);
+        const unsigned long long e = ((unsigned long long)k1 << 32) | tmin[q];
+        for (uint32_t tries = 0; tries < pcap; ++tries) {
+          if (atomicCAS(&wv[h], 0ull, e) == 0ull) break;
+          h = (h + 1 == pcap) ? 0 : h + 1;
+        }
+      }
+    }
+    wave_sync();
+    uint64_t *T = A.rec1 + 2ull * r0;
+    for (uint32_t q = lane; q < pcap; q += 64) T[q] = wv[q];
+    if (lane == 0) A.dir[bin] = ((uint64_t)r0 << 32) | pcap;
+    wave_sync();
+    r0 = q0;
+    r1 = q1;
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
   }
 }
 
 // --------------------------------------------------------------- resolve ----
 __global__ __launch_bounds__(256) void k_bq_resolve(BinnedLaunch A) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= A.n * (int64_t)A.bands) return;
-  const int64_t i = t / A.bands;
-  const uint32_t j = (uint32_t)(t - i * A.bands);
-  const ItemPos hp = item_hashes(A, i, j);
-  bool hit = true;
-  for (uint32_t l = 0; l < A.k && hit; ++l) {
-    const uint64_t g = umulhi64(hp.h1 + (uint64_t)l * hp.h2, A.m_bits);
-    const uint64_t lbin = g >> A.bin_bits;
-    const uint64_t bin = (uint64_t)j * A.bins_per_band + lbin;
-    const uint32_t r0 = A.off2[bin], r1 = A.off2[bin + 1];
-    const uint32_t cap = 2 * (r1 - r0);
-    const uint32_t lb = (uint32_t)(g - (lbin << A.bin_bits));
-    const uint64_t *T = A.table + 2ull * r0;
-    uint32_t h = slot_of(lb, cap);
-    uint32_t val = kNoFs;
-    bool found = false;
-    for (uint32_t tries = 0; tries < cap; ++tries) {
-      const uint64_t e = T[h];
-      const uint32_t key = (uint32_t)(e >> 32);
-      if (key == lb + 1) {
-        val = (uint32_t)e;
-        found = true;
-        break;
-      }
-      if (key == 0) break;
-      h = (h + 1 == cap) ? 0 : h + 1;
-    }
-    if (!found || val == kNoFs) {
-      atomicOr(A.status, 2u);  // every probed bit was published by its bin
-      hit = false;
-      break;
-    }
-    if (val != kInit && val >= (uint32_t)i) hit = false;
-  }
-  A.hitb[t] = hit ? 1 : 0;
-}
-
-__global__ __launch_bounds__(256) void k_bq_flags(BinnedLaunch A) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
   if (i >= A.n) return;
-  const uint8_t *hb = A.hitb + i * (int64_t)A.bands;
-  uint8_t f = 0;
-  for (uint32_t j = 0; j < A.bands; ++j) f |= hb[j];
-  A.flags[i] = f;
+  const BinnedGeometry &G = A.G;
+  uint8_t flag = 0;
+  for (uint32_t j = 0; j < A.bands && !flag; ++j) {
+    if (!A.res0[(int64_t)j * A.n + i]) continue;
+    const uint64_t key = A.keys[(int64_t)j * A.n + i];
+    const uint64_t h1 = fmix64(key ^ A.salt1), h2 = fmix64(key ^ A.salt2) | 1ull;
+    bool hit = true;
+    for (uint32_t l = 1; l < A.k && hit; ++l) {
+      const uint64_t g = umulhi64(h1 + (uint64_t)l * h2, A.m_bits);
+      const uint64_t lbin = g >> G.bin_bits;
+      const uint64_t d = A.dir[(uint64_t)j * G.bins_per_band + lbin];
+      const uint32_t pcap = (uint32_t)d;
+      const uint64_t *T = A.rec1 + 2ull * (d >> 32);
+      const uint32_t lb = (uint32_t)(g - (lbin << G.bin_bits));
+      bool found = false;
+      uint32_t v = 0;
+      uint32_t h = pcap ? slot_of(lb, pcap) : 0;
+      for (uint32_t tries = 0; tries < pcap; ++tries) {
+        const uint64_t e = T[h];
+        const uint32_t ek = (uint32_t)(e >> 32);
+        if (ek == lb + 1) {
+          v = (uint32_t)e;
+          found = true;
+          break;
+        }
+        if (ek == 0) break;
+        h = (h + 1 == pcap) ? 0 : h + 1;
+      }
+      // not published: the only document probing the bit is this one
+      hit = found && (v == kInit || v < (uint32_t)i);
+    }
+    if (hit) flag = 1;
+  }
+  A.flags[i] = flag;
 }
 
 inline unsigned grid1(uint64_t n, unsigned bs) {
@@ -384,64 +655,69 @@ inline unsigned grid1(uint64_t n, unsigned bs) {
   return (unsigned)(g == 0 ? 1 : g);
 }
 
+inline uint32_t ceil_log2(uint64_t x) {
+  uint32_t s = 0;
+  while (s < 63 && (1ull << s) < x) ++s;
+  return s;
+}
+
 }  // namespace
 
 BinnedGeometry binned_geometry(uint64_t n_docs, uint32_t bands, uint32_t k, uint64_t m_bits, uint32_t target_per_bin) {
+  (void)bands;
   BinnedGeometry G{};
   const double probes_per_band = (double)n_docs * k;
   // bits per bin so that a bin receives about target_per_bin records
   const double want = (double)m_bits * target_per_bin / (probes_per_band > 0 ? probes_per_band : 1.0);
-  uint32_t s = 6;
-  while (s < 24 && (double)(1ull << (s + 1)) <= want) ++s;
-  for (;; ++s) {
-    G.bin_bits = s;
-    G.bins_per_band = (m_bits + (1ull << s) - 1) >> s;
-    uint64_t spb = 2048 / bands;
-    if (spb < 1) spb = 1;
-    if (spb > G.bins_per_band) spb = G.bins_per_band;
-    uint64_t fb = (G.bins_per_band + spb - 1) / spb;
-    while (fb > 4096) {  // a super bin's counters live in LDS
-      spb *= 2;
-      fb = (G.bins_per_band + spb - 1) / spb;
-    }
-    G.supers_per_band = (uint32_t)((G.bins_per_band + fb - 1) / fb);
-    G.bins_per_super = (uint32_t)fb;
-    G.n_supers = G.supers_per_band * bands;
-    if (G.n_supers <= 8192 || s >= 31) break;  // local bits must fit 32-bit keys  // pass-1 histograms live in LDS too
-  }
-  const uint64_t items = n_docs * bands;
-  uint64_t ipb = (items + 1535) / 1536;
-  if (ipb < 1024) ipb = 1024;
-  G.items_per_block = (uint32_t)ipb;
-  G.n_blocks1 = (uint32_t)((items + ipb - 1) / ipb);
-  if (G.n_blocks1 == 0) G.n_blocks1 = 1;
+  uint32_t s = 6;  // nearest power of two
+  while (s < 24 && (double)(1ull << s) * 1.4142135623730951 <= want) ++s;
+  G.bin_bits = s;
+  G.bins_per_band = (m_bits + (1ull << s) - 1) >> s;
+  // split the bins of a band between the two passes: pass 1 fans out to at
+  // most 256 buckets unless pass 2 would exceed 1024 bins per bucket
+  const uint32_t t = ceil_log2(G.bins_per_band);
+  uint32_t f1 = t / 2;
+  if (f1 > 8) f1 = 8;
+  if (t > 10 && t - 10 > f1) f1 = t - 10;
+  G.bucket_bits = s + (t - f1);
+  G.bins_per_bucket = 1u << (t - f1);
+  G.buckets_per_band = (uint32_t)((m_bits + (1ull << G.bucket_bits) - 1) >> G.bucket_bits);
+  G.n_tiles = (uint32_t)((n_docs + kTileDocs - 1) / kTileDocs);
+  if (G.n_tiles == 0) G.n_tiles = 1;
+  G.direct_words = s <= 15;
   return G;
 }
 
 hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s) {
-  const uint64_t items = (uint64_t)a.n * a.bands;
-  if (items == 0) return hipSuccess;
-  const size_t lds1 = (size_t)a.n_supers * sizeof(uint32_t);
-  hipLaunchKernelGGL(k_bq_count1, dim3(a.n_blocks1), dim3(1024), lds1, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bq_rowscan, dim3(a.n_supers), dim3(1024), 0, s, a);
+  if (a.n == 0) return hipSuccess;
+  const BinnedGeometry &G = a.G;
+  if (G.buckets_per_band > kMaxF1 || G.bins_per_bucket > kMaxF2) return hipErrorInvalidValue;
+  hipError_t e;
+  const uint32_t td = keys_tile_docs(a.bands * a.rows);
+  const size_t ldsk = (size_t)td * (a.bands * a.rows + 1) * 4;
+  hipLaunchKernelGGL(k_bq_keys, dim3(grid1((uint64_t)a.n, td)), dim3(kThreads), ldsk, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bq_superscan, dim3(1), dim3(1024), 0, s, a);
+  const size_t lds1 = kTileDocs * 16 + kSub * 10 + kThreads * 4 + 3 * (size_t)((G.buckets_per_band + 3) & ~3u) * 4;
+  hipLaunchKernelGGL(k_bq_pass1<false>, dim3(G.n_tiles, a.bands), dim3(kThreads), lds1, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bq_rowshift, dim3(grid1((uint64_t)a.n_supers * a.n_blocks1, 256)), dim3(256), 0, s, a);
+  const uint32_t nb = a.bands * G.buckets_per_band;
+  hipLaunchKernelGGL(k_bq_scan_tiles, dim3(nb), dim3(kThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bq_scatter1, dim3(a.n_blocks1), dim3(1024), lds1, s, a);
+  hipLaunchKernelGGL(k_bq_scan_buckets, dim3(1), dim3(kThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bq_part2, dim3(a.n_supers), dim3(1024), (size_t)a.bins_per_super * sizeof(uint32_t), s, a);
+  hipLaunchKernelGGL(k_bq_pass1<true>, dim3(G.n_tiles, a.bands), dim3(kThreads), lds1, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const uint64_t n_bins = (uint64_t)a.bands * a.bins_per_band;
-  uint64_t gb = n_bins < 32768 ? n_bins : 32768;
-  hipLaunchKernelGGL(k_bq_bin, dim3((unsigned)gb), dim3(256), 0, s, a);
+  const size_t lds2 = kSub2 * 8 + 3 * (size_t)G.bins_per_bucket * 4 + 16 * 4;
+  hipLaunchKernelGGL(k_bq_part2, dim3(nb), dim3(kT2), lds2, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bq_resolve, dim3(grid1(items, 256)), dim3(256), 0, s, a);
+  const uint64_t n_bins = (uint64_t)a.bands * G.bins_per_band;
+  const unsigned gb = (unsigned)(n_bins < 262144 ? n_bins : 262144);
+  if (G.direct_words)
+    hipLaunchKernelGGL(k_bq_bin<true>, dim3(gb), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_bq_bin<false>, dim3(gb), dim3(64), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bq_flags, dim3(grid1((uint64_t)a.n, 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_bq_resolve, dim3(grid1((uint64_t)a.n, kThreads)), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -210,6 +210,56 @@ def test_query_insert_heavy_crosstalk_every_chunking(gpu, chunk_docs, qi_mode):
 
 
 @QI_MODES
+def test_query_insert_full_batch_over_loaded_filters(gpu, qi_mode):
+    """A whole 65,536-signature batch at the 1M-document workload's filter
+    size (n = 1e6, p = 1e-6 per band), after 300,000 earlier documents were
+    inserted, with 30% one-band repeats (half of them inside the batch):
+    every flag and every filter word equals the sequential result."""
+    B = 65536
+    sigs = synth.signature_batch(0, B, 128, 16, 8, B, 0.3, 0.5, seed=21).numpy().view(np.uint32)
+    pre = synth.signature_batch(0, 300_000, 128, 16, 8, 300_000, 0.0, 0.0, seed=22).numpy().view(np.uint32)
+    g, o = _pair(gpu, n=1_000_000, fp=1e-6, qi_mode=qi_mode)
+    o.insert(pre)
+    g.write_filters(torch.as_tensor(o.filters().view(np.int64)).cuda(), docs_inserted=len(pre))
+    want = o.query_insert(sigs)
+    got = g.query_insert(torch.as_tensor(sigs.view(np.int32)).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(g.read_filters().cpu().numpy().view(np.uint64), o.filters())
+    assert g.info()["device_status"] == 0
+    assert 0.1 < want.mean() < 0.3
+    g.close()
+
+
+@QI_MODES
+def test_query_insert_sparse_bins_with_repeats(gpu, qi_mode):
+    """Chunks far smaller than the filters (bins wider than 2^17 bits: their
+    words are looked up by hash rather than held whole), with in-batch
+    repeats sharing every bit of a band."""
+    rng = np.random.default_rng(23)
+    n, P, r = 6000, 128, 8
+    sigs = _random_sigs(rng, n, P)
+    rep = np.flatnonzero(rng.random(n) < 0.3)
+    rep = rep[rep > 0]
+    for i in rep:
+        s = int(rng.integers(max(0, i - 3000), i))
+        j = int(rng.integers(0, 16))
+        sigs[i, j * r:(j + 1) * r] = sigs[s, j * r:(j + 1) * r]
+    want = _qi_case(gpu, sigs, chunk_docs=2500, n=10_000_000, fp=1e-5, qi_mode=qi_mode)
+    assert want[rep].all()
+
+
+@QI_MODES
+def test_query_insert_identical_documents_sparse_bins(gpu, qi_mode):
+    """Thousands of identical documents in one chunk over wide bins: the bins
+    holding their bits exceed the LDS tables and take the global-memory path."""
+    rng = np.random.default_rng(24)
+    sigs = np.concatenate([_random_sigs(rng, 500, 128), np.repeat(_random_sigs(rng, 1, 128), 3000, axis=0),
+                           _random_sigs(rng, 500, 128)])
+    want = _qi_case(gpu, sigs, n=10_000_000, fp=1e-5, qi_mode=qi_mode)
+    assert want[501:3500].all() and not want[500]
+
+
+@QI_MODES
 def test_query_insert_split_into_calls_and_streams(gpu, qi_mode):
     """Document order is host call order, whatever stream each call uses."""
     rng = np.random.default_rng(10)
