@@ -6,11 +6,11 @@
 // in-chunk order of its bits in LDS:
 //
 //   keys      (k_bq_keys): band key of every (document, band), band-major;
-//   pass 1    (k_bq_pass1<false>, scans, k_bq_pass1<true>): one block per
-//             (band, tile of 1024 documents) computes the k positions of its
+//   pass 1    (k_bq_count1, scans, k_bq_scatter1): one block per (band,
+//             tile of 1024 documents) computes the k positions of its
 //             documents and writes 64-bit records
 //                 [probe-0 flag : 1][document : 23][bit position : 40]
-//             into buckets of consecutive bins, staging each 4096-record
+//             into buckets of consecutive bins, staging each 16,384-record
 //             sub-tile in LDS so that every bucket's records leave as one
 //             contiguous run;
 //   pass 2    (k_bq_part2): one block per bucket counts its bins, publishes
@@ -44,14 +44,12 @@ namespace lb {
 namespace {
 
 constexpr uint32_t kThreads = 256;
-constexpr uint32_t kSub = 4096;               // records staged per sub-tile
-constexpr uint32_t kPer = kSub / kThreads;    // records per thread per sub-tile
 constexpr uint32_t kInit = 0xFFFFFFFFu;       // bit set before the chunk
 constexpr uint32_t kNoFs = 0xFFFFFFFEu;       // no document recorded yet
 constexpr uint64_t kMask40 = (1ull << 40) - 1;
 constexpr uint32_t kDocMask = (1u << 23) - 1;
 constexpr uint64_t kProbe0 = 1ull << 63;
-constexpr uint32_t kMaxF1 = 2048;
+constexpr uint32_t kMaxF1 = 1024;
 constexpr uint32_t kKeysLds = 8192;           // signature words staged per keys block
 
 __host__ __device__ inline uint32_t keys_tile_docs(uint32_t br) { return br >= kKeysLds ? 1u : kKeysLds / br; }
@@ -64,8 +62,15 @@ __device__ __forceinline__ uint32_t slot_of(uint32_t key, uint32_t cap) {
   return (uint32_t)(((uint64_t)(h2 ^ (h2 >> 13)) * cap) >> 32);
 }
 
-// Exclusive scan of in[0..n) into out[0..n) (may alias) by a 256-thread
-// block of NT threads: each thread sums a run of consecutive entries, the
+// Workgroup barrier for LDS only: waits for this wave's LDS operations, not
+// for its global stores, which stay in flight across the barrier (no kernel
+// here reads back global memory written by another wave of its workgroup
+// except the global-table path of the bin kernel, which uses device-scope
+// atomics and fences).
+__device__ __forceinline__ void sync_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Exclusive scan of in[0..n) into out[0..n) (may alias) by a block of NT
+// threads: each thread sums a run of consecutive entries, the
 // runs are scanned within each wave by shuffles and across the waves through
 // part[] (NT / 64 words of LDS).  Returns the total.  Every thread of the block must call
 // it; it ends with a barrier.
@@ -83,7 +88,7 @@ __device__ uint32_t block_scan(const uint32_t *in, uint32_t *out, uint32_t n, ui
     if (lane >= off) x += y;
   }
   if (lane == 63) part[wave] = x;
-  __syncthreads();
+  sync_lds();
   uint32_t base = 0, total = 0;
 #pragma unroll
   for (uint32_t w = 0; w < NT / 64; ++w) {
@@ -97,7 +102,7 @@ __device__ uint32_t block_scan(const uint32_t *in, uint32_t *out, uint32_t n, ui
     out[q] = run;
     run += v;
   }
-  __syncthreads();
+  sync_lds();
   return total;
 }
 
@@ -135,86 +140,101 @@ __global__ __launch_bounds__(256) void k_bq_keys(BinnedLaunch A) {
 }
 
 // ---------------------------------------------------------------- pass 1 ----
-// Block (tile, band j).  COUNT: per-bucket record counts of the block.
-// SCATTER: the records, written to counts-derived offsets.
-template <bool SCATTER>
-__global__ __launch_bounds__(256) void k_bq_pass1(BinnedLaunch A) {
-  extern __shared__ __align__(16) uint8_t smem[];
-  const BinnedGeometry &G = A.G;
-  const uint32_t F1 = G.buckets_per_band;
-  const uint32_t F1r = (F1 + 3) & ~3u;
-  uint64_t *h1 = (uint64_t *)smem;                  // [kTileDocs]
-  uint64_t *h2 = h1 + kTileDocs;                    // [kTileDocs]
-  uint64_t *stage = h2 + kTileDocs;                 // [kSub]
-  uint32_t *part = (uint32_t *)(stage + kSub);      // [256]
-  uint32_t *hist = part + kThreads;                 // [F1]
-  uint32_t *lstart = hist + F1r;                    // [F1]
-  uint32_t *cur = lstart + F1r;                     // [F1]
-  uint16_t *sb = (uint16_t *)(cur + F1r);           // [kSub]
-  const uint32_t j = blockIdx.y, tile = blockIdx.x;
-  const int64_t d0 = (int64_t)tile * kTileDocs;
-  const uint32_t nd = (uint32_t)min((int64_t)kTileDocs, A.n - d0);
+// Block (tile of 1024 documents, band j).  k_bq_count1: per-bucket record
+// counts of the block.  k_bq_scatter1 (1024 threads, one block per compute
+// unit): the records, staged in LDS by bucket in sub-tiles of 16,384 so that
+// each bucket's share leaves as one run, written at counts-derived offsets.
+constexpr uint32_t kT1 = 1024;
+constexpr uint32_t kPer1 = 16;
+constexpr uint32_t kSub1 = kT1 * kPer1;
+
+__device__ __forceinline__ void tile_hashes(const BinnedLaunch &A, uint32_t j, int64_t d0, uint32_t nd, uint64_t *h1,
+                                            uint64_t *h2) {
   const uint64_t *K = A.keys + (int64_t)j * A.n + d0;
-  for (uint32_t d = threadIdx.x; d < nd; d += kThreads) {
+  for (uint32_t d = threadIdx.x; d < nd; d += blockDim.x) {
     const uint64_t key = K[d];
     h1[d] = fmix64(key ^ A.salt1);
     h2[d] = fmix64(key ^ A.salt2) | 1ull;
   }
-  const uint64_t row = ((uint64_t)j * F1) * G.n_tiles + tile;  // + f * n_tiles
-  for (uint32_t f = threadIdx.x; f < F1; f += kThreads) {
-    hist[f] = 0;
-    if (SCATTER) cur[f] = A.bstart[(uint64_t)j * F1 + f] + A.counts[row + (uint64_t)f * G.n_tiles];
-  }
-  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_bq_count1(BinnedLaunch A) {
+  __shared__ uint64_t h1[kTileDocs], h2[kTileDocs];
+  extern __shared__ uint32_t hist[];  // [F1]
+  const BinnedGeometry &G = A.G;
+  const uint32_t F1 = G.buckets_per_band;
+  const uint32_t j = blockIdx.y, tile = blockIdx.x;
+  const int64_t d0 = (int64_t)tile * kTileDocs;
+  const uint32_t nd = (uint32_t)min((int64_t)kTileDocs, A.n - d0);
+  tile_hashes(A, j, d0, nd, h1, h2);
+  for (uint32_t f = threadIdx.x; f < F1; f += kThreads) hist[f] = 0;
+  sync_lds();
   const uint32_t total = kTileDocs * A.k;
-  if (!SCATTER) {
-    for (uint32_t q = threadIdx.x; q < total; q += kThreads) {
-      const uint32_t d = q & (kTileDocs - 1), l = q >> kTileLog;
-      if (d >= nd) continue;
-      const uint64_t g = umulhi64(h1[d] + (uint64_t)l * h2[d], A.m_bits);
-      atomicAdd(&hist[(uint32_t)(g >> G.bucket_bits)], 1u);
-    }
-    __syncthreads();
-    for (uint32_t f = threadIdx.x; f < F1; f += kThreads) A.counts[row + (uint64_t)f * G.n_tiles] = hist[f];
-    return;
+  for (uint32_t q = threadIdx.x; q < total; q += kThreads) {
+    const uint32_t d = q & (kTileDocs - 1), l = q >> kTileLog;
+    if (d >= nd) continue;
+    const uint64_t g = umulhi64(h1[d] + (uint64_t)l * h2[d], A.m_bits);
+    atomicAdd(&hist[(uint32_t)(g >> G.bucket_bits)], 1u);
   }
-  for (uint32_t q0 = 0; q0 < total; q0 += kSub) {
-    uint64_t rec[kPer];
-    uint32_t bk[kPer], rk[kPer];
+  sync_lds();
+  const uint64_t row = ((uint64_t)j * F1) * G.n_tiles + tile;  // + f * n_tiles
+  for (uint32_t f = threadIdx.x; f < F1; f += kThreads) A.counts[row + (uint64_t)f * G.n_tiles] = hist[f];
+}
+
+__global__ __launch_bounds__(1024) void k_bq_scatter1(BinnedLaunch A) {
+  extern __shared__ __align__(16) uint8_t smem[];
+  const BinnedGeometry &G = A.G;
+  const uint32_t F1 = G.buckets_per_band;
+  const uint32_t F1r = (F1 + 3) & ~3u;
+  uint64_t *stage = (uint64_t *)smem;              // [kSub1]
+  uint64_t *h1 = stage + kSub1;                    // [kTileDocs]
+  uint64_t *h2 = h1 + kTileDocs;                   // [kTileDocs]
+  uint32_t *hist = (uint32_t *)(h2 + kTileDocs);   // [F1]
+  uint32_t *lstart = hist + F1r;                   // [F1]
+  uint32_t *cur = lstart + F1r;                    // [F1]
+  uint32_t *part = cur + F1r;                      // [16]
+  const uint32_t j = blockIdx.y, tile = blockIdx.x;
+  const int64_t d0 = (int64_t)tile * kTileDocs;
+  const uint32_t nd = (uint32_t)min((int64_t)kTileDocs, A.n - d0);
+  tile_hashes(A, j, d0, nd, h1, h2);
+  const uint64_t row = ((uint64_t)j * F1) * G.n_tiles + tile;  // + f * n_tiles
+  for (uint32_t f = threadIdx.x; f < F1; f += kT1) {
+    hist[f] = 0;
+    cur[f] = A.bstart[(uint64_t)j * F1 + f] + A.counts[row + (uint64_t)f * G.n_tiles];
+  }
+  sync_lds();
+  const uint32_t total = kTileDocs * A.k;
+  for (uint32_t q0 = 0; q0 < total; q0 += kSub1) {
+    uint64_t rec[kPer1];
+    uint32_t rk[kPer1];
 #pragma unroll
-    for (uint32_t u = 0; u < kPer; ++u) {
-      const uint32_t q = q0 + u * kThreads + threadIdx.x;
+    for (uint32_t u = 0; u < kPer1; ++u) {
+      const uint32_t q = q0 + u * kT1 + threadIdx.x;
       const uint32_t d = q & (kTileDocs - 1), l = q >> kTileLog;
-      bk[u] = 0xFFFFFFFFu;
+      rec[u] = ~0ull;
       if (q < total && d < nd) {
         const uint64_t g = umulhi64(h1[d] + (uint64_t)l * h2[d], A.m_bits);
-        const uint32_t f = (uint32_t)(g >> G.bucket_bits);
-        bk[u] = f;
-        rk[u] = atomicAdd(&hist[f], 1u);
+        rk[u] = atomicAdd(&hist[(uint32_t)(g >> G.bucket_bits)], 1u);
         rec[u] = (l == 0 ? kProbe0 : 0ull) | ((uint64_t)(d0 + d) << 40) | g;
       }
     }
-    __syncthreads();
-    const uint32_t cnt = block_scan(hist, lstart, F1, part);
+    sync_lds();
+    const uint32_t cnt = block_scan<kT1>(hist, lstart, F1, part);
 #pragma unroll
-    for (uint32_t u = 0; u < kPer; ++u) {
-      if (bk[u] != 0xFFFFFFFFu) {
-        const uint32_t p = lstart[bk[u]] + rk[u];
-        stage[p] = rec[u];
-        sb[p] = (uint16_t)bk[u];
-      }
+    for (uint32_t u = 0; u < kPer1; ++u)
+      if (rec[u] != ~0ull) stage[lstart[(uint32_t)((rec[u] & kMask40) >> G.bucket_bits)] + rk[u]] = rec[u];
+    sync_lds();
+    for (uint32_t p = threadIdx.x; p < cnt; p += kT1) {
+      const uint64_t r = stage[p];
+      const uint32_t f = (uint32_t)((r & kMask40) >> G.bucket_bits);
+      A.rec1[cur[f] + (p - lstart[f])] = r;
     }
-    __syncthreads();
-    for (uint32_t p = threadIdx.x; p < cnt; p += kThreads) {
-      const uint32_t f = sb[p];
-      A.rec1[cur[f] + (p - lstart[f])] = stage[p];
-    }
-    __syncthreads();
-    for (uint32_t f = threadIdx.x; f < F1; f += kThreads) {
+    sync_lds();
+    for (uint32_t f = threadIdx.x; f < F1; f += kT1) {
       cur[f] += hist[f];
       hist[f] = 0;
     }
-    __syncthreads();
+    sync_lds();
   }
 }
 
@@ -267,7 +287,7 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
     cur[b] = 0;
     h[b] = 0;
   }
-  __syncthreads();
+  sync_lds();
   for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
     uint64_t g[kPer2];
 #pragma unroll
@@ -279,7 +299,7 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
     for (uint32_t u = 0; u < kPer2; ++u)
       if (g[u] != ~0ull) atomicAdd(&cur[(uint32_t)((g[u] >> G.bin_bits) - first_bin)], 1u);
   }
-  __syncthreads();
+  sync_lds();
   block_scan<kT2>(cur, cur, F2, part);
   for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
     cur[b] += s0;
@@ -287,7 +307,7 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
   }
   if (q + 1 == A.bands * G.buckets_per_band && threadIdx.x == 0)
     A.off2[(uint64_t)A.bands * G.bins_per_band] = A.n_records;
-  __syncthreads();
+  sync_lds();
   for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
     uint64_t rec[kPer2];
     uint32_t rk[kPer2];
@@ -297,23 +317,23 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
       rec[u] = r < s1 ? A.rec1[r] : ~0ull;
       if (rec[u] != ~0ull) rk[u] = atomicAdd(&h[(uint32_t)(((rec[u] & kMask40) >> G.bin_bits) - first_bin)], 1u);
     }
-    __syncthreads();
+    sync_lds();
     const uint32_t cnt = block_scan<kT2>(h, lstart, F2, part);
 #pragma unroll
     for (uint32_t u = 0; u < kPer2; ++u)
       if (rec[u] != ~0ull) stage[lstart[(uint32_t)(((rec[u] & kMask40) >> G.bin_bits) - first_bin)] + rk[u]] = rec[u];
-    __syncthreads();
+    sync_lds();
     for (uint32_t p = threadIdx.x; p < cnt; p += kT2) {
       const uint64_t r = stage[p];
       const uint32_t b = (uint32_t)(((r & kMask40) >> G.bin_bits) - first_bin);
       A.rec2[cur[b] + (p - lstart[b])] = r;
     }
-    __syncthreads();
+    sync_lds();
     for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
       cur[b] += h[b];
       h[b] = 0;
     }
-    __syncthreads();
+    sync_lds();
   }
 }
 
@@ -675,6 +695,13 @@ BinnedGeometry binned_geometry(uint64_t n_docs, uint32_t bands, uint32_t k, uint
   G.bins_per_band = (m_bits + (1ull << s) - 1) >> s;
   // split the bins of a band between the two passes: pass 1 fans out to at
   // most 256 buckets unless pass 2 would exceed 1024 bins per bucket
+  // at most 2^20 bins per band (1024 x 1024 over the two passes): wider bins
+  // beyond that (only for chunks of more than ~1.9e8 probes per band)
+  while (s < 39 && ceil_log2(G.bins_per_band) > 20) {
+    ++s;
+    G.bin_bits = s;
+    G.bins_per_band = (m_bits + (1ull << s) - 1) >> s;
+  }
   const uint32_t t = ceil_log2(G.bins_per_band);
   uint32_t f1 = t / 2;
   if (f1 > 8) f1 = 8;
@@ -697,15 +724,15 @@ hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s) {
   const size_t ldsk = (size_t)td * (a.bands * a.rows + 1) * 4;
   hipLaunchKernelGGL(k_bq_keys, dim3(grid1((uint64_t)a.n, td)), dim3(kThreads), ldsk, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds1 = kTileDocs * 16 + kSub * 10 + kThreads * 4 + 3 * (size_t)((G.buckets_per_band + 3) & ~3u) * 4;
-  hipLaunchKernelGGL(k_bq_pass1<false>, dim3(G.n_tiles, a.bands), dim3(kThreads), lds1, s, a);
+  hipLaunchKernelGGL(k_bq_count1, dim3(G.n_tiles, a.bands), dim3(kThreads), (size_t)G.buckets_per_band * 4, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const uint32_t nb = a.bands * G.buckets_per_band;
   hipLaunchKernelGGL(k_bq_scan_tiles, dim3(nb), dim3(kThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bq_scan_buckets, dim3(1), dim3(kThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bq_pass1<true>, dim3(G.n_tiles, a.bands), dim3(kThreads), lds1, s, a);
+  const size_t lds1 = kSub1 * 8 + kTileDocs * 16 + 3 * (size_t)((G.buckets_per_band + 3) & ~3u) * 4 + 16 * 4;
+  hipLaunchKernelGGL(k_bq_scatter1, dim3(G.n_tiles, a.bands), dim3(kT1), lds1, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t lds2 = kSub2 * 8 + 3 * (size_t)G.bins_per_bucket * 4 + 16 * 4;
   hipLaunchKernelGGL(k_bq_part2, dim3(nb), dim3(kT2), lds2, s, a);
