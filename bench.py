@@ -95,7 +95,14 @@ def cpu_baseline(wl, corpus, n_docs):
                       f"MinHash + in-order query-insert, single thread, {dt:.1f} s"}
 
 
-SECTOR = 64  # bytes per random HBM access (one read-modify-write of a 64-B sector per probe)
+SECTOR = 64  # bytes per random HBM access
+
+
+def qi_algorithmic_bytes(steps, batch, probes, new_bits, num_perm):
+    """Algorithmic HBM bytes of `steps` query-insert batches: one sector read
+    per probe, one sector write per newly set bit, the signatures read once
+    and one flag byte per document."""
+    return SECTOR * (steps * probes + new_bits) + steps * batch * (4 * num_perm + 1)
 
 
 def _events(n):
@@ -139,6 +146,8 @@ def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
 
     stream = torch.cuda.current_stream()
     ev = _events(args.steps)
+    bits0 = sum(idx.count_set_bits())
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         b = args.warmup + s
@@ -149,6 +158,7 @@ def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
         ev[s][2].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    new_bits = sum(idx.count_set_bits()) - bits0
     assert idx.info()["device_status"] == 0
 
     mh_ms = [ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)]
@@ -159,7 +169,8 @@ def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
     ops = [sh * (OPS_PER_SHINGLE_HASH + wl.num_perm * OPS_PER_SHINGLE_PERM) for sh in shingles]
     mh_achieved = float(np.mean([o / (t * 1e-3) for o, t in zip(ops, mh_ms)]))
     probes = B * wl.bands * idx.k
-    qi_achieved = float(np.mean([probes * 2 * SECTOR / (t * 1e-3) for t in qi_ms]))
+    qi_bytes = qi_algorithmic_bytes(args.steps, B, probes, new_bits, wl.num_perm)
+    qi_achieved = qi_bytes / (float(np.sum(qi_ms)) * 1e-3)
     minhash_roof = {
         "bound": "alu",
         "kernel": "k_minhash (incl. its 0xFFFFFFFF pre-fill)",
@@ -178,6 +189,8 @@ def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
         "unit": "GB/s",
         "frac": qi_achieved / 8e12,
         "traffic": None,
+        "algorithmic_bytes_per_batch": qi_bytes / args.steps,
+        "new_bits_per_batch": new_bits / args.steps,
         "probes_per_s": float(np.mean([probes / (t * 1e-3) for t in qi_ms])),
     }
     dominant = minhash_roof if np.mean(mh_ms) >= np.mean(qi_ms) else qi_roof
@@ -292,6 +305,8 @@ def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     ev = _events(args.steps)
+    bits0 = sum(idx.count_set_bits())
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         b = args.warmup + s
@@ -300,10 +315,12 @@ def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
         ev[s][1].record(stream)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    new_bits = sum(idx.count_set_bits()) - bits0
     assert idx.info()["device_status"] == 0
     qi_ms = [ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)]
     probes = B * wl.bands * idx.k
-    ach = float(np.mean([probes * 2 * SECTOR / (t * 1e-3) for t in qi_ms]))
+    qi_bytes = qi_algorithmic_bytes(args.steps, B, probes, new_bits, wl.num_perm)
+    ach = qi_bytes / (float(np.sum(qi_ms)) * 1e-3)
     rep, _ = synth.signature_repeat_info(args.warmup * B, args.steps * B, wl.bands, B, ex["repeat_frac"],
                                          ex["in_batch_frac"], wl.corpus_seed, device=dev)
     fl = flags[args.warmup:].reshape(-1)
@@ -316,6 +333,8 @@ def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
             "bound": "hbm",
             "kernel": "query-insert (all kernels of a batch's in-order test-and-set)",
             "achieved": ach / 1e9, "peak": 8000.0, "unit": "GB/s", "frac": ach / 8e12, "traffic": None,
+            "algorithmic_bytes_per_batch": qi_bytes / args.steps,
+            "new_bits_per_batch": new_bits / args.steps,
             "probes_per_s": float(np.mean([probes / (t * 1e-3) for t in qi_ms])),
         },
         "repeats_flagged": float(fl[rep].float().mean().item()),

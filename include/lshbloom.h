@@ -181,6 +181,13 @@ int lshbloom_read_filters(lshbloom_t *h, void *dst, uint64_t offset, uint64_t nb
 int lshbloom_write_filters(lshbloom_t *h, const void *src, uint64_t offset, uint64_t nbytes,
                            uint64_t docs_inserted, lshbloom_stream_t stream);
 
+/* Number of set bits of each band's filter, written to out[bands] (host
+ * memory), counted after the handle's previous calls; synchronous.  At the
+ * k of Section 4.5's sizing about half of a filter's bits are set after
+ * expected_n documents, so the count tracks how full the index is; the
+ * difference over a call is the number of bits that call set. */
+int lshbloom_count_set_bits(lshbloom_t *h, uint64_t *out, lshbloom_stream_t stream);
+
 /* Parameters, sizes and counters of the handle. */
 int lshbloom_info(const lshbloom_t *h, lshbloom_info_t *out);
 

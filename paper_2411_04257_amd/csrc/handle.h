@@ -24,6 +24,7 @@ struct lshbloom {
   uint64_t *d_masks = nullptr;
   uint8_t *d_hitb = nullptr;
   uint32_t *d_status = nullptr;
+  uint64_t *d_count = nullptr;  // per-band set-bit counts [bands]
   uint64_t chunk_docs = 0;
   uint64_t workspace_bytes = 0;
   // binned query-insert workspace

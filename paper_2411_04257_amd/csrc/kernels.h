@@ -53,6 +53,9 @@ hipError_t launch_band_keys(const BloomLaunch &a, hipStream_t s);
 hipError_t launch_query_insert_chunk(const BloomLaunch &a, uint64_t table_slots, hipStream_t s);
 hipError_t launch_query(const BloomLaunch &a, hipStream_t s);
 hipError_t launch_insert(const BloomLaunch &a, hipStream_t s);
+// out[j] += set bits of words[j * words_per_band .. (j + 1) * words_per_band).
+hipError_t launch_popcount(const uint64_t *words, uint64_t words_per_band, uint32_t bands, uint64_t *out,
+                           hipStream_t s);
 
 constexpr uint64_t kTableEmpty = ~0ull;
 constexpr int kIdxBits = 18;  // doc index within a chunk

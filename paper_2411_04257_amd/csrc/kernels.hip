@@ -207,6 +207,26 @@ __global__ __launch_bounds__(kBlock) void k_minhash(MinhashLaunch A) {
   if (cur >= 0) flush(cur);
 }
 
+// Set bits of a band's words; one block per (range of words, band).
+__global__ __launch_bounds__(kBlock) void k_popcount(const uint64_t *words, uint64_t words_per_band,
+                                                     uint64_t per_block, uint64_t *out) {
+  __shared__ unsigned long long part[kBlock / 64];
+  const uint64_t *W = words + (uint64_t)blockIdx.y * words_per_band;
+  const uint64_t w0 = (uint64_t)blockIdx.x * per_block;
+  const uint64_t w1 = min(words_per_band, w0 + per_block);
+  unsigned long long c = 0;
+  for (uint64_t w = w0 + threadIdx.x; w < w1; w += kBlock) c += __popcll(W[w]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int q = 0; q < kBlock / 64; ++q) t += part[q];
+    atomicAdd((unsigned long long *)&out[blockIdx.y], t);
+  }
+}
+
 __device__ __forceinline__ uint64_t table_slot(uint64_t key, uint64_t mask) {
   return fmix64(key * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull) & mask;
 }
@@ -363,6 +383,15 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_u64, dim3(fill_grid(n)), dim3(kBlock), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_popcount(const uint64_t *words, uint64_t words_per_band, uint32_t bands, uint64_t *out,
+                           hipStream_t s) {
+  if (bands == 0 || words_per_band == 0) return hipSuccess;
+  const uint64_t per_block = 64 * 1024;  // words per block
+  const uint64_t gx = (words_per_band + per_block - 1) / per_block;
+  hipLaunchKernelGGL(k_popcount, dim3((unsigned)gx, bands), dim3(kBlock), 0, s, words, words_per_band, per_block, out);
   return hipGetLastError();
 }
 

@@ -86,6 +86,7 @@ void free_all(lshbloom *h) {
   if (h->d_masks) (void)hipFree(h->d_masks);
   if (h->d_hitb) (void)hipFree(h->d_hitb);
   if (h->d_status) (void)hipFree(h->d_status);
+  if (h->d_count) (void)hipFree(h->d_count);
   if (h->d_counts1) (void)hipFree(h->d_counts1);
   if (h->d_bstart) (void)hipFree(h->d_bstart);
   if (h->d_off2) (void)hipFree(h->d_off2);
@@ -449,6 +450,7 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   }
   LB_ALLOC(h->d_coef, prm.num_perm * sizeof(lb::PermCoef));
   LB_ALLOC(h->d_status, 256);
+  LB_ALLOC(h->d_count, (size_t)prm.bands * 8);
 #undef LB_ALLOC
   if ((e = hipMemcpy(h->d_coef, coef.data(), coef.size() * sizeof(lb::PermCoef), hipMemcpyHostToDevice)) !=
           hipSuccess ||
@@ -618,6 +620,29 @@ int lshbloom_read_filters(lshbloom_t *h, void *dst, uint64_t offset, uint64_t nb
   if (e != hipSuccess) return fail_hip(nullptr, e, "read_filters: copy");
   e = end_ordered(h, s);
   if (e != hipSuccess) return fail_hip(nullptr, e, "read_filters: event");
+  return LSHBLOOM_OK;
+}
+
+int lshbloom_count_set_bits(lshbloom_t *h, uint64_t *out, lshbloom_stream_t stream) {
+  if (!h) return check_ready(h);
+  if (!out) {
+    set_err("count_set_bits: out is NULL");
+    return LSHBLOOM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(h->mu);
+  int rc = check_ready(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = begin_ordered(h, s);
+  if (e != hipSuccess) return fail_hip(h, e, "count_set_bits: stream wait");
+  if ((e = lb::launch_fill_u64(h->d_count, h->prm.bands, 0, s)) != hipSuccess ||
+      (e = lb::launch_popcount(h->d_filters, h->words_per_band, h->prm.bands, h->d_count, s)) != hipSuccess)
+    return fail_hip(h, e, "count_set_bits: launch");
+  e = end_ordered(h, s);
+  if (e != hipSuccess) return fail_hip(h, e, "count_set_bits: event");
+  if ((e = hipMemcpyAsync(out, h->d_count, (size_t)h->prm.bands * 8, hipMemcpyDeviceToHost, s)) != hipSuccess ||
+      (e = hipStreamSynchronize(s)) != hipSuccess)
+    return fail_hip(h, e, "count_set_bits: copy");
   return LSHBLOOM_OK;
 }
 

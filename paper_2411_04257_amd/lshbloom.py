@@ -97,7 +97,7 @@ class PipelineInfo(ctypes.Structure):
 EXPORTS = [
     "lshbloom_create", "lshbloom_create_ex", "lshbloom_destroy", "lshbloom_minhash", "lshbloom_query_insert",
     "lshbloom_query", "lshbloom_insert", "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters",
-    "lshbloom_info", "lshbloom_p_band_from_eff", "lshbloom_optimal_bands", "lshbloom_last_error",
+    "lshbloom_count_set_bits", "lshbloom_info", "lshbloom_p_band_from_eff", "lshbloom_optimal_bands", "lshbloom_last_error",
     "lshbloom_pipeline_create", "lshbloom_pipeline_submit", "lshbloom_pipeline_wait", "lshbloom_pipeline_poll",
     "lshbloom_pipeline_info", "lshbloom_pipeline_destroy",
 ]
@@ -127,6 +127,7 @@ def load(path: str = LIB_PATH):
     L.lshbloom_band_keys.argtypes = [vp, vp, i64, vp, vp]
     L.lshbloom_read_filters.argtypes = [vp, vp, u64, u64, vp]
     L.lshbloom_write_filters.argtypes = [vp, vp, u64, u64, u64, vp]
+    L.lshbloom_count_set_bits.argtypes = [vp, vp, vp]
     L.lshbloom_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.lshbloom_p_band_from_eff.argtypes = [ctypes.c_double, u32]
     L.lshbloom_p_band_from_eff.restype = ctypes.c_double
@@ -147,8 +148,8 @@ def load(path: str = LIB_PATH):
     L.lshbloom_last_error.argtypes = []
     L.lshbloom_last_error.restype = ctypes.c_char_p
     for name in ("lshbloom_minhash", "lshbloom_query_insert", "lshbloom_query", "lshbloom_insert",
-                 "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters", "lshbloom_info",
-                 "lshbloom_optimal_bands"):
+                 "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters",
+                 "lshbloom_count_set_bits", "lshbloom_info", "lshbloom_optimal_bands"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -279,6 +280,12 @@ class LSHBloom:
         ptr = out.data_ptr()
         _check(load().lshbloom_read_filters(self._h, ctypes.c_void_p(ptr), 0, nbytes, _stream()))
         return out
+
+    def count_set_bits(self) -> list:
+        """Set bits of each band's filter (synchronous)."""
+        out = (ctypes.c_uint64 * self.bands)()
+        _check(load().lshbloom_count_set_bits(self._h, ctypes.cast(out, ctypes.c_void_p), _stream()))
+        return [int(v) for v in out]
 
     def write_filters(self, words: torch.Tensor, docs_inserted: int | None = None) -> None:
         if not words.is_contiguous():

@@ -61,6 +61,7 @@ def test_bad_parameters_rejected_without_device(lib):
 def test_null_handle_calls_fail_cleanly(lib):
     assert lib.lshbloom_query_insert(None, None, 0, None, None) == -1
     assert lib.lshbloom_minhash(None, None, None, 0, None, None) == -1
+    assert lib.lshbloom_count_set_bits(None, None, None) == -1
     lib.lshbloom_destroy(None)
 
 

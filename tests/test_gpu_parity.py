@@ -311,6 +311,31 @@ def test_write_and_read_filters_round_trip(gpu, qi_mode):
     g.close()
 
 
+@QI_MODES
+def test_count_set_bits_matches_oracle_filters(gpu, qi_mode):
+    """Per-band set-bit counts equal the popcount of the oracle's filter words,
+    and their growth over a call equals the bits that call set."""
+    rng = np.random.default_rng(15)
+    g, o = _pair(gpu, n=5000, fp=1e-3, qi_mode=qi_mode)
+    assert g.count_set_bits() == [0] * 16
+
+    def popc(words):
+        return np.unpackbits(words.view(np.uint8).reshape(16, -1), axis=1).sum(axis=1).tolist()
+
+    first = _random_sigs(rng, 3000, 128)
+    o.query_insert(first)
+    g.query_insert(torch.as_tensor(first.view(np.int32)).cuda())
+    before = popc(o.filters())
+    assert g.count_set_bits() == before
+    nxt = np.concatenate([first[:500], _random_sigs(rng, 1500, 128)])
+    o.query_insert(nxt)
+    g.query_insert(torch.as_tensor(nxt.view(np.int32)).cuda())
+    after = popc(o.filters())
+    assert g.count_set_bits() == after
+    assert all(a > b for a, b in zip(after, before))
+    g.close()
+
+
 def test_injected_fault_poisons_handle(gpu):
     os.environ["LSHBLOOM_FAULT_AT"] = "2"
     try:
