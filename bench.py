@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="after the timed steps, one device-to-device copy of this many bytes "
                          "(calibrates the HBM byte counters against a plain copy)")
+    ap.add_argument("--probe-hbm", type=int, default=0, metavar="GB",
+                    help="instead of a workload: measure the memory system's ceilings with torch's own kernels "
+                         "(streaming copy, random 8-byte gather and scatter over a GB-sized buffer) and exit")
     a = ap.parse_args()
     default_steps = {"c2": (13, 2), "c3": (4, 1), "c4": (20, 2), "c5": (0, 0)}[a.workload]
     if a.steps is None:
@@ -420,6 +423,49 @@ def run_serve(args, wl, torch, np, lshbloom, synth, dev):
     return res, None, None
 
 
+def probe_hbm(torch, gb):
+    """Ceilings of the memory system, measured with torch's kernels (not this
+    library's): a streaming device copy, and uniformly random 8-byte gathers
+    and scatters over a `gb`-GB buffer.  Each random access touches its own
+    64-byte sector; the gather also reads its index and writes its value
+    sequentially (16 bytes per access)."""
+    n = gb * (1 << 27)
+    buf = torch.zeros(n, dtype=torch.int64, device="cuda")
+    m = 1 << 27
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5)
+    idx = torch.randint(0, n, (m,), device="cuda", generator=gen)
+    vals = torch.empty(m, dtype=torch.int64, device="cuda")
+    src = torch.ones(1 << 30, dtype=torch.int64, device="cuda")
+    dst = torch.empty_like(src)
+
+    def timed(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+            fn()
+            b.record()
+            b.synchronize()
+            ms.append(a.elapsed_time(b))
+        return min(ms)
+
+    t_copy = timed(lambda: dst.copy_(src))
+    t_gather = timed(lambda: torch.index_select(buf, 0, idx, out=vals))
+    t_scatter = timed(lambda: buf.index_copy_(0, idx, vals))
+    return {
+        "probe": "hbm ceilings with torch kernels",
+        "buffer_GB": gb,
+        "copy_GBps_read_plus_write": 2 * src.numel() * 8 / (t_copy * 1e-3) / 1e9,
+        "gather_accesses_per_s": m / (t_gather * 1e-3),
+        "gather_GBps_at_64B_sectors": m * 64 / (t_gather * 1e-3) / 1e9,
+        "scatter_accesses_per_s": m / (t_scatter * 1e-3),
+        "accesses": m,
+    }
+
+
 DESCRIPTIONS = {
     "c2": "plain method on GPU: 1M-doc synthetic corpus (Zipf(1.1)/50k-vocab uint32 tokens, lognormal lengths "
           "median 3000 sigma 0.8 cap 50000, 20% near-dups J 0.6-0.95), 5-shingles, num_perm 128, 16 bands x 8 rows, "
@@ -449,6 +495,9 @@ def main():
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.probe_hbm:
+        print(json.dumps(probe_hbm(torch, args.probe_hbm)), flush=True)
+        return
     wl = synth.WORKLOADS[args.workload]
     higher = True
     if args.workload == "c4":
