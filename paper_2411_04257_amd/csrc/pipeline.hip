@@ -4,13 +4,19 @@
 //   host:   CSR check, length bucketing (documents grouped by token count so
 //           that each bucket runs its own persistent MinHash launch with its
 //           own grid), bucket descriptors into pinned memory;
-//   slot stream (graph G1): H2D tokens + descriptors, signature pre-fill,
+//   copy stream: H2D tokens + descriptors, one batch after another in
+//           submission order (each copy gets the link to itself; on this
+//           device a host-to-device copy runs as a blit kernel, so copies
+//           of two slots started together would share the link and finish
+//           together, and neither batch's MinHash could start early);
+//   slot stream (graph G1): after its batch's copy, signature pre-fill and
 //           one MinHash launch per non-empty bucket;
 //   query-insert stream (graph G2): after G1 of this batch and after every
 //           earlier filter call of the handle, the in-order query-insert and
 //           the D2H copy of the flags.
-// Two slots alternate, so the host work and MinHash of batch t+1 overlap the
-// query-insert of batch t, while query-inserts stay in submission order.
+// Two slots alternate, so the copy of batch t+1 overlaps the MinHash of
+// batch t and the MinHash of batch t+1 its query-insert, while query-inserts
+// stay in submission order.
 // Per-batch device work is captured into a hipGraph per slot and stage and
 // replayed (the executable graph is updated in place when only launch
 // parameters change).  A small autotuner times candidate bucket edges and
@@ -35,7 +41,7 @@ constexpr uint32_t kMaxBuckets = 4;
 
 struct Slot {
   hipStream_t stream = nullptr;
-  hipEvent_t mh_done = nullptr, done = nullptr;
+  hipEvent_t copied = nullptr, mh_done = nullptr, done = nullptr;
   int64_t *h_desc = nullptr;     // pinned bucket descriptors
   uint32_t *h_tokens = nullptr;  // pinned token staging (used when the caller's buffer is pageable)
   uint8_t *h_flags = nullptr;    // pinned flags
@@ -63,6 +69,7 @@ struct lshbloom_pipeline {
   Buckets bk;
   int cus = 256;
   hipStream_t qi_stream = nullptr;
+  hipStream_t copy_stream = nullptr;
   Slot slot[kSlots];
   int64_t next_ticket = 0;
   bool tuned = false;
@@ -301,6 +308,7 @@ void free_pipeline(lshbloom_pipeline *pl) {
     if (S.stream) (void)hipStreamSynchronize(S.stream);
     if (S.g1) (void)hipGraphExecDestroy(S.g1);
     if (S.g2) (void)hipGraphExecDestroy(S.g2);
+    if (S.copied) (void)hipEventDestroy(S.copied);
     if (S.mh_done) (void)hipEventDestroy(S.mh_done);
     if (S.done) (void)hipEventDestroy(S.done);
     if (S.stream) (void)hipStreamDestroy(S.stream);
@@ -315,6 +323,10 @@ void free_pipeline(lshbloom_pipeline *pl) {
   if (pl->qi_stream) {
     (void)hipStreamSynchronize(pl->qi_stream);
     (void)hipStreamDestroy(pl->qi_stream);
+  }
+  if (pl->copy_stream) {
+    (void)hipStreamSynchronize(pl->copy_stream);
+    (void)hipStreamDestroy(pl->copy_stream);
   }
 }
 
@@ -360,10 +372,12 @@ lshbloom_pipeline_t *lshbloom_pipeline_create(lshbloom_t *h, const lshbloom_pipe
   hipError_t e = hipGetDeviceProperties(&dp, h->device);
   if (e == hipSuccess) pl->cus = dp.multiProcessorCount;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->qi_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->copy_stream, hipStreamNonBlocking);
   const uint64_t P = h->prm.num_perm;
   for (int q = 0; q < kSlots && e == hipSuccess; ++q) {
     Slot &S = pl->slot[q];
     e = hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&S.copied, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S.mh_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S.h_desc, desc_words(p->max_docs) * 8, hipHostMallocDefault);
@@ -443,16 +457,21 @@ int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offse
     if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: token copy");
     rc = autotune(pl, S, h_offsets, n_docs);
     if (rc) return rc;
+    // the slot's device buffers are rewritten on the copy stream below
+    if ((e = hipStreamSynchronize(S.stream)) != hipSuccess) return fail_hip(nullptr, e, "pipeline: tuning");
   }
   BucketView views[kMaxBuckets];
   build_buckets(pl->bk, h_offsets, n_docs, S.h_desc, views);
   const Buckets bk = pl->bk;
-  auto g1_body = [&]() -> hipError_t {
-    hipError_t x = hipMemcpyAsync(S.d_tokens, src, (size_t)n_tok * 4, hipMemcpyHostToDevice, S.stream);
-    if (x == hipSuccess) x = hipMemcpyAsync(S.d_desc, S.h_desc, desc_words(n_docs) * 8, hipMemcpyHostToDevice, S.stream);
-    if (x == hipSuccess) x = enqueue_minhash(pl, S, views, n_docs, bk);
-    return x;
-  };
+  // inputs on the copy stream, in submission order (the slot's previous batch
+  // is complete: collect() waited for it)
+  e = hipMemcpyAsync(S.d_tokens, src, (size_t)n_tok * 4, hipMemcpyHostToDevice, pl->copy_stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(S.d_desc, S.h_desc, desc_words(n_docs) * 8, hipMemcpyHostToDevice, pl->copy_stream);
+  if (e == hipSuccess) e = hipEventRecord(S.copied, pl->copy_stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(S.stream, S.copied, 0);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: input copy");
+  auto g1_body = [&]() -> hipError_t { return enqueue_minhash(pl, S, views, n_docs, bk); };
   e = pl->prm.use_graph ? run_graph(pl, S.stream, S.g1, g1_body) : g1_body();
   if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: MinHash stage");
   e = hipEventRecord(S.mh_done, S.stream);
