@@ -1,0 +1,116 @@
+"""GPU parity at the full sizes of the 10M-document batched workload (one
+1M-document chunk, 15.3 GB of filters) and of the filter-scale stream (1M
+signatures per chunk, 191.7 GB of filters), in the launch configuration the
+benchmark times (binned query-insert, one chunk per batch).
+
+Where the oracle cannot recompute a whole batch it checks what it can compute
+one by one: a prefix of the stream (its flags depend only on earlier
+documents), sampled signatures, the bits every sampled document must have set
+after the batch (Section 2.4: inserted keys are always found), and, on the
+filter-scale stream, that every band-key repeat is flagged and that no other
+signature is, at a filter fill where the Bloom false-positive rate is ~1e-80.
+"""
+
+import ctypes
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_04257_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _index(gpu, wl):
+    # the benchmark's configuration: one chunk per batch
+    return gpu.LSHBloom(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed,
+                        chunk_docs=wl.batch, workspace_budget=24 * wl.batch * wl.bands * 40 + (64 << 20))
+
+
+def _word(gpu, g, band, word):
+    out = ctypes.c_uint64(0)
+    rc = gpu.load().lshbloom_read_filters(g._h, ctypes.byref(out), (band * g.words_per_band + word) * 8, 8, None)
+    assert rc == 0
+    return out.value
+
+
+def _assert_bits_set(gpu, g, sig, bands, rows, salts, m, k):
+    for j in range(bands):
+        key = oracle.band_key(sig, j, rows, salts[0])
+        for pos in oracle.positions(key, salts[1], salts[2], m, k):
+            pos = int(pos)
+            assert (_word(gpu, g, j, pos >> 6) >> (pos & 63)) & 1, (j, pos)
+
+
+def test_c3_chunk_prefix_samples_and_inserted_bits(gpu):
+    wl = synth.WORKLOADS["c3"]
+    B = wl.batch
+    corpus = synth.make_corpus(wl, device="cuda", n_docs=B, seed=wl.corpus_seed)
+    g = _index(gpu, wl)
+    info = g.info()
+    assert info["binned_chunk_docs"] == B and info["filter_bytes"] == 15_336_093_440
+    sigs = g.minhash(corpus.offsets, corpus.tokens)
+    flags = g.query_insert(sigs).cpu().numpy()
+    gs = sigs.cpu().numpy().view(np.uint32)
+    assert g.info()["device_status"] == 0
+    off = corpus.offsets.cpu().numpy()
+    tok = corpus.tokens.cpu().numpy().view(np.uint32)
+    strong = np.flatnonzero(corpus.is_dup & (corpus.target_j >= 0.93))
+    del corpus, sigs
+    o = oracle.OracleIndex(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
+    assert (o.m_bits, o.k) == (g.m_bits, g.k)
+    pre = 4096
+    want = o.minhash(off[:pre + 1], tok)
+    np.testing.assert_array_equal(gs[:pre], want)
+    np.testing.assert_array_equal(flags[:pre], o.query_insert(want))
+    a, b, salts = o.coeffs()
+    o.close()
+    rng = np.random.default_rng(3)
+    sample = np.sort(rng.choice(np.arange(pre, B), 48, replace=False))
+    for d in sample:
+        sig = oracle.minhash_doc(tok[off[d]:off[d + 1]], 5, a, b)
+        np.testing.assert_array_equal(gs[d], sig)
+    for d in sample[:8]:
+        sig = oracle.minhash_doc(tok[off[d]:off[d + 1]], 5, a, b)
+        _assert_bits_set(gpu, g, sig, wl.bands, wl.rows, salts, g.m_bits, g.k)
+    # near-duplicates whose source is earlier in the batch and nearly identical
+    # (target Jaccard >= 0.93) are flagged; short documents (lengths from 20
+    # tokens) realise a lower Jaccard than the target after an edit or two
+    assert len(strong) > 1000 and flags[strong].mean() > 0.9
+    g.close()
+
+
+def test_c4_full_filters_repeats_and_inserted_bits(gpu):
+    wl = synth.WORKLOADS["c4"]
+    B, n_batches = wl.batch, 3
+    ex = wl.extra
+    g = _index(gpu, wl)
+    assert g.info()["filter_bytes"] == 191_701_167_616
+    flags = []
+    for t in range(n_batches):
+        s = synth.signature_batch(t * B, B, wl.num_perm, wl.bands, wl.rows, B, ex["repeat_frac"],
+                                  ex["in_batch_frac"], wl.corpus_seed, device="cuda")
+        flags.append(g.query_insert(s).cpu())
+        del s
+    flags = torch.cat(flags).numpy()
+    assert g.info()["device_status"] == 0
+    rep, _ = synth.signature_repeat_info(0, n_batches * B, wl.bands, B, ex["repeat_frac"], ex["in_batch_frac"],
+                                         wl.corpus_seed)
+    rep = rep.numpy()
+    assert rep.mean() > 0.25
+    assert flags[rep].all()          # a repeated band key was inserted before: always found
+    assert not flags[~rep].any()     # fill ~2e-3 per band: P(false positive) ~ (2e-3)^33 per band
+    # every bit of sampled signatures is set afterwards
+    o = oracle.OracleIndex(wl.num_perm, wl.bands, wl.rows, 1000, 1e-3, wl.index_seed)  # coefficients and salts only
+    _, _, salts = o.coeffs()
+    o.close()
+    m, k = oracle.params(wl.expected_n, wl.fp_rate)
+    assert (m, k) == (g.m_bits, g.k)
+    rng = np.random.default_rng(4)
+    for i in rng.choice(n_batches * B, 6, replace=False):
+        sig = synth.signature_batch(int(i), 1, wl.num_perm, wl.bands, wl.rows, B, ex["repeat_frac"],
+                                    ex["in_batch_frac"], wl.corpus_seed).numpy().view(np.uint32)[0]
+        _assert_bits_set(gpu, g, sig, wl.bands, wl.rows, salts, m, k)
+    g.close()
