@@ -211,7 +211,8 @@ typedef struct lshbloom_pipeline_params {
   uint64_t max_tokens;        /* capacity: tokens per submitted batch */
   uint32_t n_buckets;         /* 1..4 MinHash length buckets; 0 = chosen by the autotuner (or 1) */
   uint64_t bucket_edges[3];   /* token-length edges: bucket b holds lengths in [edge[b-1], edge[b]) */
-  uint32_t waves_per_cu[4];   /* persistent MinHash waves per compute unit, per bucket; 0 = 16 */
+  uint32_t waves_per_cu[4];   /* persistent MinHash waves per compute unit, per bucket; 0 = sized by the
+                                 bucket's tokens (one wave per ~2,048, 16 to 256 per compute unit) */
   uint32_t use_graph;         /* 1: capture each slot's device work in a hipGraph and replay it */
   uint32_t autotune;          /* 1: on the first batch, time candidate bucket edges and grid sizes */
   const char *tune_cache;     /* text file for autotuned choices (read, then appended); NULL = none */

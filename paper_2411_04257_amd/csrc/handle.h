@@ -36,7 +36,8 @@ struct lshbloom {
   uint32_t *d_counts1 = nullptr, *d_bstart = nullptr, *d_off2 = nullptr;
   uint64_t *d_rec1 = nullptr, *d_rec2 = nullptr, *d_bkeys = nullptr, *d_dir = nullptr;
   uint8_t *d_res0 = nullptr;
-  int minhash_waves = 0;
+  int minhash_waves = 0;  // persistent MinHash grid; 0 = sized per call
+  int cus = 0;            // compute units of the device
   hipEvent_t last = nullptr;
   bool has_last = false;
   bool poisoned = false;

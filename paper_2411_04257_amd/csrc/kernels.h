@@ -57,6 +57,19 @@ hipError_t launch_insert(const BloomLaunch &a, hipStream_t s);
 hipError_t launch_popcount(const uint64_t *words, uint64_t words_per_band, uint32_t bands, uint64_t *out,
                            hipStream_t s);
 
+// Size of the persistent MinHash grid.  Waves own equal token ranges; many
+// more waves than fit at once (up to 256 per compute unit) let the hardware
+// balance the tail, and one wave per ~2,048 tokens keeps each range long
+// enough to amortise its start.  When only the document count is known on the
+// host, four waves per document stand in for the token count.
+inline int minhash_waves_for_tokens(int cus, uint64_t tokens) {
+  uint64_t w = tokens / 2048;
+  const uint64_t lo = 16ull * (uint64_t)cus, hi = 256ull * (uint64_t)cus;
+  w = w < lo ? lo : (w > hi ? hi : w);
+  return (int)(w < 4 ? 4 : w / 4 * 4);
+}
+inline int minhash_waves_for_docs(int cus, uint64_t n_docs) { return minhash_waves_for_tokens(cus, n_docs * 4 * 2048); }
+
 constexpr uint64_t kTableEmpty = ~0ull;
 constexpr int kIdxBits = 18;  // doc index within a chunk
 constexpr uint64_t kMaxChunkDocs = (1ull << kIdxBits) - 1;

@@ -61,8 +61,12 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
   return (int64_t)(((uint64_t)rhi << 32) | rlo);
 }
 
+// Waves per SIMD the register budget must allow (97 VGPRs would give 4 at
+// PPL = 2; 96 gives 5).
+constexpr int minhash_min_waves(int ppl) { return ppl <= 2 ? 5 : (ppl <= 4 ? 4 : 3); }
+
 template <int PPL, int WFIX>
-__global__ __launch_bounds__(kBlock) void k_minhash(MinhashLaunch A) {
+__global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(MinhashLaunch A) {
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t n_docs = A.n_docs;

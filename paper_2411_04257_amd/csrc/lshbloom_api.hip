@@ -416,8 +416,10 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
     delete h;
     return nullptr;
   }
-  // Persistent MinHash grid: 16 waves per compute unit.
-  h->minhash_waves = dp.multiProcessorCount * 16;
+  // Persistent MinHash grid: sized per call (minhash_waves_for_docs) unless
+  // fixed by the environment.
+  h->cus = dp.multiProcessorCount;
+  h->minhash_waves = 0;
   if (const char *mw = std::getenv("LSHBLOOM_MINHASH_WAVES")) {
     int v = std::atoi(mw);
     if (v >= 4) h->minhash_waves = (v / 4) * 4;
@@ -509,7 +511,7 @@ int lshbloom_minhash(lshbloom_t *h, const int64_t *d_offsets, const uint32_t *d_
   a.sigs = d_sigs;
   a.num_perm = h->prm.num_perm;
   a.w = h->prm.shingle_width;
-  a.waves = h->minhash_waves;
+  a.waves = h->minhash_waves ? h->minhash_waves : lb::minhash_waves_for_docs(h->cus, (uint64_t)n_docs);
   e = lb::launch_minhash(a, s);
   if (e != hipSuccess) return fail_hip(nullptr, e, "minhash: launch");
   return LSHBLOOM_OK;

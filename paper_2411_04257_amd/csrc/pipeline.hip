@@ -58,7 +58,7 @@ struct Slot {
 struct Buckets {
   uint32_t n = 1;
   uint64_t edges[kMaxBuckets - 1] = {0, 0, 0};
-  uint32_t waves_per_cu[kMaxBuckets] = {16, 16, 16, 16};
+  uint32_t waves_per_cu[kMaxBuckets] = {0, 0, 0, 0};  // 0: sized by the bucket's tokens
 };
 
 }  // namespace
@@ -89,7 +89,7 @@ using lbh::set_err;
 uint64_t desc_words(uint64_t max_docs) { return kMaxBuckets + 3 * max_docs + kMaxBuckets; }
 
 struct BucketView {
-  int64_t count;
+  int64_t count, tokens;
   uint64_t voff, shift, row;  // word offsets into the descriptor array
 };
 
@@ -126,6 +126,7 @@ void build_buckets(const Buckets &bk, const int64_t *off, int64_t n, int64_t *de
     vsum[b] += L;
     desc[views[b].voff + q + 1] = vsum[b];
   }
+  for (uint32_t b = 0; b < kMaxBuckets; ++b) views[b].tokens = vsum[b];
 }
 
 hipError_t enqueue_minhash(lshbloom_pipeline *pl, Slot &S, const BucketView *views, int64_t n,
@@ -143,7 +144,8 @@ hipError_t enqueue_minhash(lshbloom_pipeline *pl, Slot &S, const BucketView *vie
     a.sigs = S.d_sigs;
     a.num_perm = h->prm.num_perm;
     a.w = h->prm.shingle_width;
-    a.waves = std::max(4, (int)(bk.waves_per_cu[b] * pl->cus) / 4 * 4);
+    a.waves = bk.waves_per_cu[b] ? std::max(4, (int)(bk.waves_per_cu[b] * pl->cus) / 4 * 4)
+                                 : lb::minhash_waves_for_tokens(pl->cus, (uint64_t)views[b].tokens);
     a.tok_shift = S.d_desc + views[b].shift;
     a.row_ids = S.d_desc + views[b].row;
     e = lb::launch_minhash(a, S.stream);
@@ -259,7 +261,7 @@ int autotune(lshbloom_pipeline *pl, Slot &S, const int64_t *off, int64_t n) {
   std::vector<Buckets> cands;
   const uint64_t edge_sets[][3] = {{0, 0, 0}, {512, 0, 0}, {256, 8192, 0}, {64, 1024, 16384}};
   const uint32_t nbs[] = {1, 2, 3, 4};
-  const uint32_t waves[] = {8, 16, 24};
+  const uint32_t waves[] = {0, 64, 256};  // per compute unit; 0 = by the bucket's tokens
   for (int es = 0; es < 4; ++es)
     for (uint32_t w : waves) {
       Buckets b;
