@@ -35,8 +35,9 @@ OPS_PER_SHINGLE_PERM = 8.5
 INT32_VALU_PEAK = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
 # HBM bytes per token that k_minhash moved, from rocprofv3 FETCH_SIZE (x2.0) and
 # WRITE_SIZE (x1.0) scaled by a 1 GiB copy (profiles/k_minhash_c2_counters.md):
-# 1.126e9 B for a 2.72e8-token batch.  Valid for the kernel version profiled.
-MINHASH_HBM_BYTES_PER_TOKEN = 1.126e9 / 2.7207e8
+# 1.202e9 B for a 2.717e8-token batch (65,536 waves).  Valid for the kernel
+# version and grid sizing profiled.
+MINHASH_HBM_BYTES_PER_TOKEN = 1.2021e9 / 2.7175e8
 
 
 def parse():
