@@ -356,17 +356,6 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t lds_insert(uint32_t *keys, uint32_t key1, uint32_t cap, uint32_t *status) {
-  uint32_t h = slot_of(key1 - 1, cap);
-  for (uint32_t tries = 0; tries < cap; ++tries) {
-    const uint32_t old = atomicCAS(&keys[h], 0u, key1);
-    if (old == 0u || (old & ~kMulti) == key1) return h;
-    h = (h + 1 == cap) ? 0 : h + 1;
-  }
-  atomicOr(status, 4u);  // cannot happen: cap >= 2 x distinct keys
-  return 0;
-}
-
 // A bin with more records than the wave's LDS tables hold: its table (every
 // distinct bit, 2 slots per record) is built in the bin's own slots of the
 // table area with device atomics; filter bits are set after every record has
@@ -497,12 +486,16 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     const uint32_t W = (uint32_t)min((uint64_t)1 << (G.bin_bits - 6), A.words_per_band - (b0 >> 6));
     // this bin's loads first: its words (direct) or each record's word; then
     // the next bin's records
-    for (uint32_t q = lane; q < cap; q += 64) {
-      tkey[q] = 0;
-      tmin[q] = kNoFs;
-      if (!DIRECT) {
-        wk[q] = 0;
-        wv[q] = 0;
+#pragma unroll
+    for (uint32_t t = 0; t < kWTab / 64; ++t) {
+      const uint32_t q = t * 64 + lane;
+      if (q < cap) {
+        tkey[q] = 0;
+        tmin[q] = kNoFs;
+        if (!DIRECT) {
+          wk[q] = 0;
+          wv[q] = 0;
+        }
       }
     }
     if (DIRECT) {
@@ -527,95 +520,142 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     }
     load_recs(nbin, q0, q1, nrec);
     wave_sync();
-    // phase A: state before the chunk, bit table, least document
-    uint32_t slot[kWPer];
-    uint32_t clear = 0;  // records whose bit was clear before the chunk
+    // phase A: insert every record's bit into the bit table.  A lane's
+    // records probe in rounds (one compare-and-swap per record per round,
+    // issued together), so their LDS round trips overlap.
+    uint32_t slot[kWPer], key1[kWPer];
+    uint32_t pend = 0, clear = 0;  // clear: the bit was clear before the chunk
 #pragma unroll
     for (uint32_t u = 0; u < kWPer; ++u) {
       slot[u] = 0;
+      key1[u] = 0;
       if (rec[u] == ~0ull) continue;
-      const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
       const uint32_t lb = (uint32_t)((rec[u] & kMask40) - b0);
       const uint64_t bit = 1ull << (lb & 63);
-      const bool init = ((DIRECT ? wv[lb >> 6] : pre[u]) & bit) != 0;
-      const uint32_t h = lds_insert(tkey, lb + 1, cap, A.status);
-      slot[u] = h;
-      if (init) {
-        tmin[h] = kInit;  // every record of this bit sees the same state
-      } else {
-        clear |= 1u << u;
-        const uint32_t old = atomicMin(&tmin[h], i);
-        if (old != kNoFs && old != i) atomicOr(&tkey[h], kMulti);
+      if (((DIRECT ? wv[lb >> 6] : pre[u]) & bit) == 0) clear |= 1u << u;
+      key1[u] = lb + 1;
+      slot[u] = slot_of(lb, cap);
+      pend |= 1u << u;
+    }
+    for (uint32_t round = 0; pend && round < cap; ++round) {
+      uint32_t old[kWPer];
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u)
+        if (pend >> u & 1u) old[u] = atomicCAS(&tkey[slot[u]], 0u, key1[u]);
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u) {
+        if (!(pend >> u & 1u)) continue;
+        if (old[u] == 0u || (old[u] & ~kMulti) == key1[u])
+          pend &= ~(1u << u);
+        else
+          slot[u] = (slot[u] + 1 == cap) ? 0 : slot[u] + 1;
       }
     }
+    if (pend) atomicOr(A.status, 4u);  // cannot happen: cap >= 2 x distinct bits
     wave_sync();
-    // phase B: OR the newly set bits into the words
-    uint32_t owner = 0, wslot[DIRECT ? 1 : kWPer];
+    // least document probing each clear bit; bits set before the chunk are
+    // marked (every record of a bit sees the same state)
 #pragma unroll
     for (uint32_t u = 0; u < kWPer; ++u) {
+      if (!key1[u]) continue;
+      if (clear >> u & 1u)
+        atomicMin(&tmin[slot[u]], (uint32_t)(rec[u] >> 40) & kDocMask);
+      else
+        tmin[slot[u]] = kInit;
+    }
+    wave_sync();
+    // phase B: probe 0 of every (document, band) is answered here; a bit whose
+    // least document is not the reader's was probed by two documents or more;
+    // the newly set bits are ORed into the words
+    uint32_t owner = 0, wslot[DIRECT ? 1 : kWPer], wpend = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      if (!key1[u]) continue;
+      const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
+      const uint32_t v = tmin[slot[u]];
+      if (rec[u] & kProbe0) A.res0[(int64_t)j * A.n + i] = (v == kInit || v < i) ? 1 : 0;
       if (!(clear >> u & 1u)) continue;
-      const uint32_t lb = (uint32_t)((rec[u] & kMask40) - b0);
-      const uint32_t lw = lb >> 6;
-      const unsigned long long bit = 1ull << (lb & 63);
+      if (v != i) atomicOr(&tkey[slot[u]], kMulti);
+      const uint32_t lb = key1[u] - 1, lw = lb >> 6;
       if (DIRECT) {
-        atomicOr(&wv[lw], bit);
+        atomicOr(&wv[lw], 1ull << (lb & 63));
         atomicOr(&wk[lw >> 5], 1u << (lw & 31));
       } else {
-        uint32_t hw = slot_of(lw, cap);
-        for (uint32_t tries = 0; tries < cap; ++tries) {
-          const uint32_t old = atomicCAS(&wk[hw], 0u, lw + 1);
-          if (old == 0u) {
-            owner |= 1u << u;  // this record writes the word back
-            wslot[u] = hw;
-            break;
-          }
-          if (old == lw + 1) break;
-          hw = (hw + 1 == cap) ? 0 : hw + 1;
-        }
-        atomicOr(&wv[hw], bit);
+        wslot[u] = slot_of(lw, cap);
+        wpend |= 1u << u;
       }
+    }
+    if (!DIRECT) {
+      // the word table, in rounds like the bit table; the record that claims
+      // a word's slot writes the word back
+      for (uint32_t round = 0; wpend && round < cap; ++round) {
+        uint32_t old[kWPer];
+#pragma unroll
+        for (uint32_t u = 0; u < kWPer; ++u)
+          if (wpend >> u & 1u) old[u] = atomicCAS(&wk[wslot[u]], 0u, ((key1[u] - 1) >> 6) + 1);
+#pragma unroll
+        for (uint32_t u = 0; u < kWPer; ++u) {
+          if (!(wpend >> u & 1u)) continue;
+          const uint32_t want = ((key1[u] - 1) >> 6) + 1;
+          if (old[u] == 0u) owner |= 1u << u;
+          if (old[u] == 0u || old[u] == want)
+            wpend &= ~(1u << u);
+          else
+            wslot[u] = (wslot[u] + 1 == cap) ? 0 : wslot[u] + 1;
+        }
+      }
+      if (wpend) atomicOr(A.status, 4u);
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u)
+        if (clear >> u & 1u) atomicOr(&wv[wslot[u]], 1ull << ((key1[u] - 1) & 63));
     }
     wave_sync();
     // changed words (this wave is their only writer in the chunk)
     if (DIRECT) {
-      for (uint32_t w = lane; w < W; w += 64)
-        if (wk[w >> 5] >> (w & 31) & 1u) F[w] = wv[w];
+#pragma unroll
+      for (uint32_t t = 0; t < kWRegion / 64; ++t) {
+        const uint32_t w = t * 64 + lane;
+        if (w < W && (wk[w >> 5] >> (w & 31) & 1u)) F[w] = wv[w];
+      }
     } else {
 #pragma unroll
       for (uint32_t u = 0; u < kWPer; ++u)
-        if (owner >> u & 1u) F[(uint32_t)((rec[u] & kMask40) - b0) >> 6] = pre[u] | wv[wslot[u]];
-    }
-    // probe 0 of every (document, band) is answered here
-#pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) {
-      if (rec[u] != ~0ull && (rec[u] & kProbe0)) {
-        const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
-        const uint32_t v = tmin[slot[u]];
-        A.res0[(int64_t)j * A.n + i] = (v == kInit || v < i) ? 1 : 0;
-      }
+        if (owner >> u & 1u) F[(key1[u] - 1) >> 6] = pre[u] | wv[wslot[u]];
     }
     // publish the bits a lookup can need (set before the chunk, or probed by
     // two documents or more)
-    uint32_t mine = 0;
-    for (uint32_t q = lane; q < cap; q += 64)
-      if (tkey[q] && (tmin[q] == kInit || (tkey[q] & kMulti))) ++mine;
+    constexpr uint32_t kSlotsPer = kWTab / 64;
+    uint32_t ib = 0;  // this lane's table rows holding a bit to publish
+#pragma unroll
+    for (uint32_t t = 0; t < kSlotsPer; ++t) {
+      const uint32_t q = t * 64 + lane;
+      if (q < cap) {
+        const uint32_t k = tkey[q];
+        if (k && (tmin[q] == kInit || (k & kMulti))) ib |= 1u << t;
+      }
+    }
+    uint32_t mine = __popc(ib);
 #pragma unroll
     for (uint32_t off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
     const uint32_t room = DIRECT ? kWRegion : kWTab;
     const uint32_t pcap = min(2 * mine, room);
     wave_sync();
-    for (uint32_t q = lane; q < pcap; q += 64) wv[q] = 0;
+#pragma unroll
+    for (uint32_t t = 0; t < kWTab / 64; ++t) {
+      const uint32_t q = t * 64 + lane;
+      if (q < pcap) wv[q] = 0;
+    }
     wave_sync();
-    for (uint32_t q = lane; q < cap; q += 64) {
-      const uint32_t key = tkey[q];
-      if (key && (tmin[q] == kInit || (key & kMulti))) {
-        const uint32_t k1 = key & ~kMulti;
-        uint32_t h = slot_of(k1 - 1, pcap);
-        const unsigned long long e = ((unsigned long long)k1 << 32) | tmin[q];
-        for (uint32_t tries = 0; tries < pcap; ++tries) {
-          if (atomicCAS(&wv[h], 0ull, e) == 0ull) break;
-          h = (h + 1 == pcap) ? 0 : h + 1;
-        }
+    while (ib) {  // few per lane: about 2 x the bin's records / 64 at most
+      const uint32_t t = __ffs(ib) - 1;
+      ib &= ib - 1;
+      const uint32_t q = t * 64 + lane;
+      const uint32_t k1 = tkey[q] & ~kMulti;
+      const unsigned long long e = ((unsigned long long)k1 << 32) | tmin[q];
+      uint32_t h = slot_of(k1 - 1, pcap);
+      for (uint32_t tries = 0; tries < pcap; ++tries) {
+        if (atomicCAS(&wv[h], 0ull, e) == 0ull) break;
+        h = (h + 1 == pcap) ? 0 : h + 1;
       }
     }
     wave_sync();
