@@ -83,6 +83,7 @@ enum {
   LSHBLOOM_ENOMEM = -2,    /* device memory (or the HBM budget) exhausted */
   LSHBLOOM_EHIP = -3,      /* HIP runtime error; message in last_error */
   LSHBLOOM_EPOISONED = -4, /* an earlier device error left the filters indeterminate */
+  LSHBLOOM_EIO = -5,       /* a file could not be opened, read or written */
 };
 
 /* Limits of this implementation. */
@@ -180,6 +181,24 @@ int lshbloom_read_filters(lshbloom_t *h, void *dst, uint64_t offset, uint64_t nb
  * saved index or a preloaded state. */
 int lshbloom_write_filters(lshbloom_t *h, const void *src, uint64_t offset, uint64_t nbytes,
                            uint64_t docs_inserted, lshbloom_stream_t stream);
+
+/* Save the index to a file (Section 4.5: the index is a persistent bit
+ * array): an 80-byte little-endian header
+ *   "LSHBLM01", num_perm, bands, rows, shingle_width (u32 each),
+ *   expected_n (u64), fp_rate (f64), seed, m_bits (u64), k, 0 (u32 each),
+ *   docs_inserted, words_per_band (u64 each)
+ * then the band-major filter words (u64 each), after the handle's previous
+ * calls.  The words pass through a 64 MB pinned host buffer, so filters far
+ * larger than host memory can be saved.  Synchronous.  LSHBLOOM_EIO if the
+ * file cannot be created or written (a partial file may remain). */
+int lshbloom_save(lshbloom_t *h, const char *path, lshbloom_stream_t stream);
+
+/* Load a file written by lshbloom_save into a handle created with the same
+ * num_perm, bands, rows, shingle_width, seed, m_bits and k (LSHBLOOM_EINVAL
+ * otherwise, filters untouched); replaces the filters and docs_inserted.
+ * Synchronous.  LSHBLOOM_EIO if the file is missing or short (the filters may
+ * then be partly overwritten: the handle is poisoned). */
+int lshbloom_load(lshbloom_t *h, const char *path, lshbloom_stream_t stream);
 
 /* Number of set bits of each band's filter, written to out[bands] (host
  * memory), counted after the handle's previous calls; synchronous.  At the

@@ -625,6 +625,138 @@ int lshbloom_read_filters(lshbloom_t *h, void *dst, uint64_t offset, uint64_t nb
   return LSHBLOOM_OK;
 }
 
+namespace {
+
+struct FileHeader {
+  char magic[8];
+  uint32_t num_perm, bands, rows, shingle_width;
+  uint64_t expected_n;
+  double fp_rate;
+  uint64_t seed, m_bits;
+  uint32_t k, reserved;
+  uint64_t docs_inserted, words_per_band;
+};
+static_assert(sizeof(FileHeader) == 80, "file header layout");
+constexpr char kMagic[8] = {'L', 'S', 'H', 'B', 'L', 'M', '0', '1'};
+constexpr size_t kStageBytes = 64ull << 20;
+
+struct PinnedStage {
+  void *p = nullptr;
+  ~PinnedStage() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+}  // namespace
+
+int lshbloom_save(lshbloom_t *h, const char *path, lshbloom_stream_t stream) {
+  if (!h) return check_ready(h);
+  if (!path) {
+    set_err("save: path is NULL");
+    return LSHBLOOM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(h->mu);
+  int rc = check_ready(h);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  PinnedStage st;
+  hipError_t e = hipHostMalloc(&st.p, kStageBytes, hipHostMallocDefault);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "save: pinned staging");
+  FILE *f = std::fopen(path, "wb");
+  if (!f) {
+    set_err("save: cannot create %s", path);
+    return LSHBLOOM_EIO;
+  }
+  FileHeader hd{};
+  std::memcpy(hd.magic, kMagic, 8);
+  hd.num_perm = h->prm.num_perm;
+  hd.bands = h->prm.bands;
+  hd.rows = h->prm.rows;
+  hd.shingle_width = h->prm.shingle_width;
+  hd.expected_n = h->prm.expected_n;
+  hd.fp_rate = h->prm.fp_rate;
+  hd.seed = h->prm.seed;
+  hd.m_bits = h->m_bits;
+  hd.k = h->k;
+  hd.docs_inserted = h->docs_inserted;
+  hd.words_per_band = h->words_per_band;
+  bool ok = std::fwrite(&hd, sizeof hd, 1, f) == 1;
+  e = begin_ordered(h, s);
+  const uint64_t total = h->m_bits / 8 * h->prm.bands;
+  for (uint64_t off = 0; ok && e == hipSuccess && off < total; off += kStageBytes) {
+    const size_t nb = (size_t)std::min<uint64_t>(kStageBytes, total - off);
+    e = hipMemcpyAsync(st.p, (const char *)h->d_filters + off, nb, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) ok = std::fwrite(st.p, 1, nb, f) == nb;
+  }
+  if (e == hipSuccess) e = end_ordered(h, s);
+  ok = (std::fclose(f) == 0) && ok;
+  if (e != hipSuccess) return fail_hip(nullptr, e, "save: copy");
+  if (!ok) {
+    set_err("save: writing %s failed", path);
+    return LSHBLOOM_EIO;
+  }
+  return LSHBLOOM_OK;
+}
+
+int lshbloom_load(lshbloom_t *h, const char *path, lshbloom_stream_t stream) {
+  if (!h) return check_ready(h);
+  if (!path) {
+    set_err("load: path is NULL");
+    return LSHBLOOM_EINVAL;
+  }
+  std::lock_guard<std::mutex> lk(h->mu);
+  int rc = check_ready(h);
+  if (rc) return rc;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) {
+    set_err("load: cannot open %s", path);
+    return LSHBLOOM_EIO;
+  }
+  FileHeader hd{};
+  if (std::fread(&hd, sizeof hd, 1, f) != 1 || std::memcmp(hd.magic, kMagic, 8) != 0) {
+    std::fclose(f);
+    set_err("load: %s is not an index file", path);
+    return LSHBLOOM_EIO;
+  }
+  if (hd.num_perm != h->prm.num_perm || hd.bands != h->prm.bands || hd.rows != h->prm.rows ||
+      hd.shingle_width != h->prm.shingle_width || hd.seed != h->prm.seed || hd.m_bits != h->m_bits ||
+      hd.k != h->k || hd.words_per_band != h->words_per_band) {
+    std::fclose(f);
+    set_err("load: %s holds an index of other parameters (P %u, b %u, r %u, w %u, seed %llu, m %llu, k %u)", path,
+            hd.num_perm, hd.bands, hd.rows, hd.shingle_width, (unsigned long long)hd.seed,
+            (unsigned long long)hd.m_bits, hd.k);
+    return LSHBLOOM_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  PinnedStage st;
+  hipError_t e = hipHostMalloc(&st.p, kStageBytes, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    std::fclose(f);
+    return fail_hip(nullptr, e, "load: pinned staging");
+  }
+  e = begin_ordered(h, s);
+  const uint64_t total = h->m_bits / 8 * h->prm.bands;
+  bool ok = true;
+  for (uint64_t off = 0; ok && e == hipSuccess && off < total; off += kStageBytes) {
+    const size_t nb = (size_t)std::min<uint64_t>(kStageBytes, total - off);
+    e = hipStreamSynchronize(s);  // the staging buffer is free again
+    if (e == hipSuccess) ok = std::fread(st.p, 1, nb, f) == nb;
+    if (e == hipSuccess && ok) e = hipMemcpyAsync((char *)h->d_filters + off, st.p, nb, hipMemcpyHostToDevice, s);
+  }
+  std::fclose(f);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e == hipSuccess) e = end_ordered(h, s);
+  if (e != hipSuccess) return fail_hip(h, e, "load: copy");
+  if (!ok) {
+    h->poisoned = true;
+    set_err("load: %s is shorter than its header says; the filters are partly overwritten", path);
+    return LSHBLOOM_EIO;
+  }
+  h->docs_inserted = hd.docs_inserted;
+  return LSHBLOOM_OK;
+}
+
 int lshbloom_count_set_bits(lshbloom_t *h, uint64_t *out, lshbloom_stream_t stream) {
   if (!h) return check_ready(h);
   if (!out) {

@@ -17,9 +17,9 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblshbloom.so")
 
-OK, EINVAL, ENOMEM, EHIP, EPOISONED = 0, -1, -2, -3, -4
+OK, EINVAL, ENOMEM, EHIP, EPOISONED, EIO = 0, -1, -2, -3, -4, -5
 QI_AUTO, QI_DIRECT, QI_BINNED = 0, 1, 2
-_CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EPOISONED: "EPOISONED"}
+_CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EPOISONED: "EPOISONED", EIO: "EIO"}
 
 
 class LSHBloomError(RuntimeError):
@@ -97,7 +97,7 @@ class PipelineInfo(ctypes.Structure):
 EXPORTS = [
     "lshbloom_create", "lshbloom_create_ex", "lshbloom_destroy", "lshbloom_minhash", "lshbloom_query_insert",
     "lshbloom_query", "lshbloom_insert", "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters",
-    "lshbloom_count_set_bits", "lshbloom_info", "lshbloom_p_band_from_eff", "lshbloom_optimal_bands", "lshbloom_last_error",
+    "lshbloom_count_set_bits", "lshbloom_save", "lshbloom_load", "lshbloom_info", "lshbloom_p_band_from_eff", "lshbloom_optimal_bands", "lshbloom_last_error",
     "lshbloom_pipeline_create", "lshbloom_pipeline_submit", "lshbloom_pipeline_wait", "lshbloom_pipeline_poll",
     "lshbloom_pipeline_info", "lshbloom_pipeline_destroy",
 ]
@@ -128,6 +128,8 @@ def load(path: str = LIB_PATH):
     L.lshbloom_read_filters.argtypes = [vp, vp, u64, u64, vp]
     L.lshbloom_write_filters.argtypes = [vp, vp, u64, u64, u64, vp]
     L.lshbloom_count_set_bits.argtypes = [vp, vp, vp]
+    L.lshbloom_save.argtypes = [vp, ctypes.c_char_p, vp]
+    L.lshbloom_load.argtypes = [vp, ctypes.c_char_p, vp]
     L.lshbloom_info.argtypes = [vp, ctypes.POINTER(Info)]
     L.lshbloom_p_band_from_eff.argtypes = [ctypes.c_double, u32]
     L.lshbloom_p_band_from_eff.restype = ctypes.c_double
@@ -149,7 +151,7 @@ def load(path: str = LIB_PATH):
     L.lshbloom_last_error.restype = ctypes.c_char_p
     for name in ("lshbloom_minhash", "lshbloom_query_insert", "lshbloom_query", "lshbloom_insert",
                  "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters",
-                 "lshbloom_count_set_bits", "lshbloom_info", "lshbloom_optimal_bands"):
+                 "lshbloom_count_set_bits", "lshbloom_save", "lshbloom_load", "lshbloom_info", "lshbloom_optimal_bands"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -280,6 +282,14 @@ class LSHBloom:
         ptr = out.data_ptr()
         _check(load().lshbloom_read_filters(self._h, ctypes.c_void_p(ptr), 0, nbytes, _stream()))
         return out
+
+    def save(self, path: str) -> None:
+        """Write the index (header + filter words) to `path` (synchronous)."""
+        _check(load().lshbloom_save(self._h, str(path).encode(), _stream()))
+
+    def load(self, path: str) -> None:
+        """Replace the filters and docs_inserted from a file written by save()."""
+        _check(load().lshbloom_load(self._h, str(path).encode(), _stream()))
 
     def count_set_bits(self) -> list:
         """Set bits of each band's filter (synchronous)."""

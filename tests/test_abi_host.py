@@ -62,6 +62,8 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.lshbloom_query_insert(None, None, 0, None, None) == -1
     assert lib.lshbloom_minhash(None, None, None, 0, None, None) == -1
     assert lib.lshbloom_count_set_bits(None, None, None) == -1
+    assert lib.lshbloom_save(None, b"x", None) == -1
+    assert lib.lshbloom_load(None, b"x", None) == -1
     lib.lshbloom_destroy(None)
 
 

@@ -336,6 +336,52 @@ def test_count_set_bits_matches_oracle_filters(gpu, qi_mode):
     g.close()
 
 
+def test_save_and_load_round_trip(gpu, tmp_path):
+    """An index saved to a file and loaded into a new handle continues the
+    stream exactly as the oracle does; the file's words are the oracle's."""
+    rng = np.random.default_rng(16)
+    first = _random_sigs(rng, 3000, 128)
+    nxt = np.concatenate([first[:400], _random_sigs(rng, 1600, 128)])
+    g, o = _pair(gpu, n=5000, fp=1e-3)
+    o.query_insert(first)
+    g.query_insert(torch.as_tensor(first.view(np.int32)).cuda())
+    path = tmp_path / "index.lshb"
+    g.save(path)
+    g.close()
+    raw = np.fromfile(path, dtype=np.uint8)
+    head = raw[:80]
+    assert bytes(head[:8]) == b"LSHBLM01"
+    np.testing.assert_array_equal(raw[80:].view(np.uint64).reshape(16, -1), o.filters())
+    h = gpu.LSHBloom(128, 16, 8, 5000, 1e-3, 42)
+    h.load(path)
+    assert h.info()["docs_inserted"] == 3000
+    want = o.query_insert(nxt)
+    got = h.query_insert(torch.as_tensor(nxt.view(np.int32)).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(got, want)
+    assert want[:400].all()
+    np.testing.assert_array_equal(h.read_filters().cpu().numpy().view(np.uint64), o.filters())
+    h.close()
+    # other parameters: rejected, filters untouched
+    other = gpu.LSHBloom(128, 16, 8, 6000, 1e-3, 42)
+    with pytest.raises(gpu.LSHBloomError) as e:
+        other.load(path)
+    assert e.value.code == gpu.EINVAL
+    assert sum(other.count_set_bits()) == 0
+    # missing and truncated files
+    with pytest.raises(gpu.LSHBloomError) as e:
+        other.load(tmp_path / "missing.lshb")
+    assert e.value.code == gpu.EIO
+    other.close()
+    short = tmp_path / "short.lshb"
+    short.write_bytes(raw[: 80 + 1000].tobytes())
+    h = gpu.LSHBloom(128, 16, 8, 5000, 1e-3, 42)
+    with pytest.raises(gpu.LSHBloomError) as e:
+        h.load(short)
+    assert e.value.code == gpu.EIO
+    assert h.info()["poisoned"] == 1
+    h.close()
+
+
 def test_injected_fault_poisons_handle(gpu):
     os.environ["LSHBLOOM_FAULT_AT"] = "2"
     try:

@@ -85,6 +85,19 @@ def test_pipeline_matches_oracle(gpu, use_graph, buckets):
         assert info["tuned"] == 1
 
 
+@pytest.mark.parametrize("use_graph", [False, True], ids=["eager", "graph"])
+def test_pipeline_binned_query_insert_matches_oracle(gpu, use_graph):
+    """Batches above the binned path's threshold (4,096 documents): its
+    kernels run inside the captured graphs and replay with new batches."""
+    off, tok = _corpus(20000, seed=35)
+    batches = [6000, 5000, 9000]
+    want_flags, want_words = _oracle_stream(off, tok, batches, n=50_000)
+    flags, words, info = _run_pipeline(gpu, off, tok, batches, n=50_000, use_graph=use_graph, autotune=False)
+    np.testing.assert_array_equal(flags, want_flags)
+    np.testing.assert_array_equal(words, want_words)
+    assert want_flags.sum() > 1000
+
+
 def test_pipeline_pinned_inputs_and_many_graph_replays(gpu):
     off, tok = _corpus(9000, seed=32)
     batches = [1500] * 6
