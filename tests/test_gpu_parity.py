@@ -111,7 +111,8 @@ def test_minhash_offsets_not_starting_at_zero(gpu):
     g.close()
 
 
-@pytest.mark.parametrize("num_perm,w", [(128, 5), (256, 5), (64, 5), (48, 5), (200, 3), (128, 1), (320, 13)])
+@pytest.mark.parametrize("num_perm,w", [(128, 5), (256, 5), (64, 5), (48, 5), (200, 3), (128, 1), (320, 13),
+                                        (512, 5), (512, 13)])
 def test_minhash_widths_and_perm_counts(gpu, num_perm, w):
     wl = synth.WORKLOADS["c3"]
     corpus = synth.make_corpus(wl, n_docs=3000, seed=11)
@@ -257,6 +258,23 @@ def test_query_insert_identical_documents_sparse_bins(gpu, qi_mode):
                            _random_sigs(rng, 500, 128)])
     want = _qi_case(gpu, sigs, n=10_000_000, fp=1e-5, qi_mode=qi_mode)
     assert want[501:3500].all() and not want[500]
+
+
+@QI_MODES
+def test_query_insert_largest_signature_and_band_counts(gpu, qi_mode):
+    """The limits of the handle: 512-value signatures, 64 bands of 8 rows,
+    with in-batch repeats of single bands."""
+    rng = np.random.default_rng(25)
+    n, P, b, r = 5000, 512, 64, 8
+    sigs = _random_sigs(rng, n, P)
+    rep = np.flatnonzero(rng.random(n) < 0.2)
+    rep = rep[rep > 0]
+    for i in rep:
+        s = int(rng.integers(0, i))
+        j = int(rng.integers(0, b))
+        sigs[i, j * r:(j + 1) * r] = sigs[s, j * r:(j + 1) * r]
+    want = _qi_case(gpu, sigs, bands=b, rows=r, n=20_000, fp=1e-4, qi_mode=qi_mode)
+    assert want[rep].all()
 
 
 @QI_MODES
