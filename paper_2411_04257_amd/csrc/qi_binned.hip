@@ -288,16 +288,27 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
     h[b] = 0;
   }
   sync_lds();
-  for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
+  {
     uint64_t g[kPer2];
 #pragma unroll
     for (uint32_t u = 0; u < kPer2; ++u) {
-      const uint32_t r = q0 + u * kT2 + threadIdx.x;
-      g[u] = r < s1 ? (A.rec1[r] & kMask40) : ~0ull;
+      const uint32_t r = s0 + u * kT2 + threadIdx.x;
+      g[u] = r < s1 ? A.rec1[r] : ~0ull;
     }
+    for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
+      uint32_t bi[kPer2];
 #pragma unroll
-    for (uint32_t u = 0; u < kPer2; ++u)
-      if (g[u] != ~0ull) atomicAdd(&cur[(uint32_t)((g[u] >> G.bin_bits) - first_bin)], 1u);
+      for (uint32_t u = 0; u < kPer2; ++u)
+        bi[u] = g[u] != ~0ull ? (uint32_t)(((g[u] & kMask40) >> G.bin_bits) - first_bin) : ~0u;
+#pragma unroll
+      for (uint32_t u = 0; u < kPer2; ++u) {
+        const uint32_t r = q0 + kSub2 + u * kT2 + threadIdx.x;
+        g[u] = r < s1 ? A.rec1[r] : ~0ull;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kPer2; ++u)
+        if (bi[u] != ~0u) atomicAdd(&cur[bi[u]], 1u);
+    }
   }
   sync_lds();
   block_scan<kT2>(cur, cur, F2, part);
@@ -308,20 +319,29 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
   if (q + 1 == A.bands * G.buckets_per_band && threadIdx.x == 0)
     A.off2[(uint64_t)A.bands * G.bins_per_band] = A.n_records;
   sync_lds();
+  // The next sub-tile's records are loaded as soon as the current ones sit in
+  // LDS, so that their latency overlaps the write-out and the barriers.
+  uint64_t rec[kPer2];
+#pragma unroll
+  for (uint32_t u = 0; u < kPer2; ++u) {
+    const uint32_t r = s0 + u * kT2 + threadIdx.x;
+    rec[u] = r < s1 ? A.rec1[r] : ~0ull;
+  }
   for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
-    uint64_t rec[kPer2];
     uint32_t rk[kPer2];
 #pragma unroll
-    for (uint32_t u = 0; u < kPer2; ++u) {
-      const uint32_t r = q0 + u * kT2 + threadIdx.x;
-      rec[u] = r < s1 ? A.rec1[r] : ~0ull;
+    for (uint32_t u = 0; u < kPer2; ++u)
       if (rec[u] != ~0ull) rk[u] = atomicAdd(&h[(uint32_t)(((rec[u] & kMask40) >> G.bin_bits) - first_bin)], 1u);
-    }
     sync_lds();
     const uint32_t cnt = block_scan<kT2>(h, lstart, F2, part);
 #pragma unroll
     for (uint32_t u = 0; u < kPer2; ++u)
       if (rec[u] != ~0ull) stage[lstart[(uint32_t)(((rec[u] & kMask40) >> G.bin_bits) - first_bin)] + rk[u]] = rec[u];
+#pragma unroll
+    for (uint32_t u = 0; u < kPer2; ++u) {
+      const uint32_t r = q0 + kSub2 + u * kT2 + threadIdx.x;
+      rec[u] = r < s1 ? A.rec1[r] : ~0ull;
+    }
     sync_lds();
     for (uint32_t p = threadIdx.x; p < cnt; p += kT2) {
       const uint64_t r = stage[p];
