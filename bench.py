@@ -17,6 +17,7 @@ and the CPU oracle timed on a bounded prefix of the same stream.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -56,6 +57,8 @@ def parse():
                     help="plain: per-batch calls on HBM-resident inputs; batched: the host-to-host pipeline "
                          "(length buckets, overlapping slots, hipGraph, autotuner) compared with per-batch "
                          "calls that copy the same host batches")
+    ap.add_argument("--batch", type=int, default=None,
+                    help="documents per batch (default: the workload's; c3 leaves it open)")
     ap.add_argument("--chunk-docs", type=int, default=None,
                     help="documents per in-order query-insert chunk (default: the batch)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -500,6 +503,8 @@ def main():
         print(json.dumps(probe_hbm(torch, args.probe_hbm)), flush=True)
         return
     wl = synth.WORKLOADS[args.workload]
+    if args.batch:
+        wl = dataclasses.replace(wl, batch=args.batch)
     higher = True
     if args.workload == "c4":
         res, corpus, idx = run_signatures(args, wl, torch, np, lshbloom, synth, dev)

@@ -454,8 +454,8 @@ __device__ void bin_global(const BinnedLaunch &A, uint32_t j, uint64_t bin, uint
 
 template <bool DIRECT>
 __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
-  __shared__ uint32_t tkey[kWTab];
-  __shared__ uint32_t tmin[kWTab];  // least document probing the bit, or kInit
+  __shared__ __align__(16) uint32_t tkey[kWTab];
+  __shared__ __align__(16) uint32_t tmin[kWTab];  // least document probing the bit, or kInit
   __shared__ unsigned long long wv[DIRECT ? kWRegion : kWTab];
   __shared__ uint32_t wk[DIRECT ? kWRegion / 32 : kWTab];  // direct: changed-word bits; else word keys
 
@@ -506,19 +506,39 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     const uint32_t W = (uint32_t)min((uint64_t)1 << (G.bin_bits - 6), A.words_per_band - (b0 >> 6));
     // this bin's loads first: its words (direct) or each record's word; then
     // the next bin's records
+    if (DIRECT) {
+      // both tables whole, 16 bytes per store
+      static_assert(kWTab % 4 == 0 && kWTab / 4 <= 192, "three stores per lane");
+      uint4 *k4 = reinterpret_cast<uint4 *>(tkey), *m4 = reinterpret_cast<uint4 *>(tmin);
+      const uint4 z = make_uint4(0u, 0u, 0u, 0u), nf = make_uint4(kNoFs, kNoFs, kNoFs, kNoFs);
 #pragma unroll
-    for (uint32_t t = 0; t < kWTab / 64; ++t) {
-      const uint32_t q = t * 64 + lane;
-      if (q < cap) {
-        tkey[q] = 0;
-        tmin[q] = kNoFs;
-        if (!DIRECT) {
+      for (uint32_t t = 0; t < 3; ++t) {
+        const uint32_t q = t * 64 + lane;
+        if (t < 2 || q < kWTab / 4) {
+          k4[q] = z;
+          m4[q] = nf;
+        }
+      }
+    } else {
+#pragma unroll
+      for (uint32_t t = 0; t < kWTab / 64; ++t) {
+        const uint32_t q = t * 64 + lane;
+        if (q < cap) {
+          tkey[q] = 0;
+          tmin[q] = kNoFs;
           wk[q] = 0;
           wv[q] = 0;
         }
       }
     }
-    if (DIRECT) {
+    const bool full = W == kWRegion;  // every bin but the last of a band
+    if (DIRECT && full) {
+      uint64_t reg[kWRegion / 64];
+#pragma unroll
+      for (uint32_t u = 0; u < kWRegion / 64; ++u) reg[u] = F[u * 64 + lane];
+#pragma unroll
+      for (uint32_t u = 0; u < kWRegion / 64; ++u) wv[u * 64 + lane] = reg[u];
+    } else if (DIRECT) {
       uint64_t reg[kWRegion / 64];
 #pragma unroll
       for (uint32_t u = 0; u < kWRegion / 64; ++u) {
@@ -599,7 +619,7 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
       const uint32_t lb = key1[u] - 1, lw = lb >> 6;
       if (DIRECT) {
         atomicOr(&wv[lw], 1ull << (lb & 63));
-        atomicOr(&wk[lw >> 5], 1u << (lw & 31));
+        if (!full) atomicOr(&wk[lw >> 5], 1u << (lw & 31));
       } else {
         wslot[u] = slot_of(lw, cap);
         wpend |= 1u << u;
@@ -631,7 +651,11 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     }
     wave_sync();
     // changed words (this wave is their only writer in the chunk)
-    if (DIRECT) {
+    if (DIRECT && full) {
+      // all of them: nearly every 64-byte sector holds a changed word
+#pragma unroll
+      for (uint32_t t = 0; t < kWRegion / 64; ++t) F[t * 64 + lane] = wv[t * 64 + lane];
+    } else if (DIRECT) {
 #pragma unroll
       for (uint32_t t = 0; t < kWRegion / 64; ++t) {
         const uint32_t w = t * 64 + lane;
