@@ -454,9 +454,11 @@ __device__ void bin_global(const BinnedLaunch &A, uint32_t j, uint64_t bin, uint
 
 template <bool DIRECT>
 __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
+  // tmin[slot]: 0 if the bit was set before the chunk, else 1 + the least
+  // document probing it (so one atomicMin serves both), kNoFs before any.
   __shared__ __align__(16) uint32_t tkey[kWTab];
-  __shared__ __align__(16) uint32_t tmin[kWTab];  // least document probing the bit, or kInit
-  __shared__ unsigned long long wv[DIRECT ? kWRegion : kWTab];
+  __shared__ __align__(16) uint32_t tmin[kWTab];
+  __shared__ __align__(16) unsigned long long wv[DIRECT ? kWRegion : kWTab];
   __shared__ uint32_t wk[DIRECT ? kWRegion / 32 : kWTab];  // direct: changed-word bits; else word keys
 
   const uint32_t lane = threadIdx.x;
@@ -464,17 +466,22 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
   const uint64_t n_bins = (uint64_t)A.bands * G.bins_per_band;
   // The records of the wave's next bin are loaded while it works on the
   // current one (records of bins above kWCap are not: bin_global reads them).
+  // A bin's records fill rows of 64; in its last row the lanes past the end
+  // repeat the bin's first record (a repeated record changes nothing: it
+  // finds its bit's slot taken by its twin, ORs the same bit and answers
+  // the same probe 0), so that every lane of a row holds a record.
   auto load_recs = [&](uint64_t b, uint32_t &q0, uint32_t &q1, uint64_t *out) {
     q0 = q1 = 0;
     if (b < n_bins) {
       q0 = A.off2[b];
       q1 = A.off2[b + 1];
     }
-    const bool small = q1 - q0 <= kWCap;
+    const uint32_t nrr = q1 - q0;
+    const bool small = nrr <= kWCap;
 #pragma unroll
     for (uint32_t u = 0; u < kWPer; ++u) {
       const uint32_t r = q0 + u * 64 + lane;
-      out[u] = (small && r < q1) ? A.rec2[r] : ~0ull;
+      out[u] = (small && u * 64 < nrr) ? A.rec2[r < q1 ? r : q0] : ~0ull;
     }
   };
   uint32_t r0, r1;
@@ -498,12 +505,14 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
       for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
       continue;
     }
+    const uint32_t nu = (nr + 63) >> 6;  // rows of records (uniform)
     const uint32_t j = (uint32_t)(bin / G.bins_per_band);
     const uint64_t lbin = bin - (uint64_t)j * G.bins_per_band;
     const uint64_t b0 = lbin << G.bin_bits;  // first bit of the bin (a multiple of 64)
     uint64_t *F = A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6);
     const uint32_t cap = 2 * nr;
     const uint32_t W = (uint32_t)min((uint64_t)1 << (G.bin_bits - 6), A.words_per_band - (b0 >> 6));
+    const bool full = W == kWRegion;  // direct: every bin but the last of a band
     // this bin's loads first: its words (direct) or each record's word; then
     // the next bin's records
     if (DIRECT) {
@@ -531,7 +540,6 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
         }
       }
     }
-    const bool full = W == kWRegion;  // every bin but the last of a band
     if (DIRECT && full) {
       uint64_t reg[kWRegion / 64];
 #pragma unroll
@@ -556,28 +564,47 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     if (!DIRECT) {
 #pragma unroll
       for (uint32_t u = 0; u < kWPer; ++u)
-        pre[u] = rec[u] != ~0ull ? F[(uint32_t)((rec[u] & kMask40) - b0) >> 6] : 0ull;
+        pre[u] = u < nu ? F[(uint32_t)((rec[u] & kMask40) - b0) >> 6] : 0ull;
     }
     load_recs(nbin, q0, q1, nrec);
     wave_sync();
     // phase A: insert every record's bit into the bit table.  A lane's
     // records probe in rounds (one compare-and-swap per record per round,
-    // issued together), so their LDS round trips overlap.
+    // issued together), so their LDS round trips overlap.  The record whose
+    // swap fills a slot owns the bit.
     uint32_t slot[kWPer], key1[kWPer];
-    uint32_t pend = 0, clear = 0;  // clear: the bit was clear before the chunk
+    uint32_t init = 0, own = 0;  // init: the bit was set before the chunk
 #pragma unroll
     for (uint32_t u = 0; u < kWPer; ++u) {
       slot[u] = 0;
       key1[u] = 0;
-      if (rec[u] == ~0ull) continue;
-      const uint32_t lb = (uint32_t)((rec[u] & kMask40) - b0);
-      const uint64_t bit = 1ull << (lb & 63);
-      if (((DIRECT ? wv[lb >> 6] : pre[u]) & bit) == 0) clear |= 1u << u;
-      key1[u] = lb + 1;
-      slot[u] = slot_of(lb, cap);
-      pend |= 1u << u;
+      if (u < nu) {
+        const uint32_t lb = (uint32_t)((rec[u] & kMask40) - b0);
+        const uint64_t word = DIRECT ? wv[lb >> 6] : pre[u];
+        init |= (uint32_t)(word >> (lb & 63) & 1ull) << u;
+        key1[u] = lb + 1;
+        // direct bins: the bit itself is uniform over the bin, so it scales
+        // to a slot directly
+        slot[u] = DIRECT ? (uint32_t)(((uint64_t)lb * cap) >> G.bin_bits) : slot_of(lb, cap);
+      }
     }
-    for (uint32_t round = 0; pend && round < cap; ++round) {
+    uint32_t pend = 0;
+    {
+      uint32_t old[kWPer];
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u)
+        if (u < nu) old[u] = atomicCAS(&tkey[slot[u]], 0u, key1[u]);
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u) {
+        if (u >= nu) continue;
+        if (old[u] == 0u) own |= 1u << u;
+        if (old[u] != 0u && old[u] != key1[u]) {
+          pend |= 1u << u;
+          slot[u] = (slot[u] + 1 == cap) ? 0 : slot[u] + 1;
+        }
+      }
+    }
+    for (uint32_t round = 1; pend && round < cap; ++round) {
       uint32_t old[kWPer];
 #pragma unroll
       for (uint32_t u = 0; u < kWPer; ++u)
@@ -585,7 +612,8 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
 #pragma unroll
       for (uint32_t u = 0; u < kWPer; ++u) {
         if (!(pend >> u & 1u)) continue;
-        if (old[u] == 0u || (old[u] & ~kMulti) == key1[u])
+        if (old[u] == 0u) own |= 1u << u;
+        if (old[u] == 0u || old[u] == key1[u])
           pend &= ~(1u << u);
         else
           slot[u] = (slot[u] + 1 == cap) ? 0 : slot[u] + 1;
@@ -593,34 +621,30 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     }
     if (pend) atomicOr(A.status, 4u);  // cannot happen: cap >= 2 x distinct bits
     wave_sync();
-    // least document probing each clear bit; bits set before the chunk are
-    // marked (every record of a bit sees the same state)
+    // least document (+1) probing each clear bit, 0 for bits set before the
+    // chunk (every record of a bit sees the same state)
 #pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) {
-      if (!key1[u]) continue;
-      if (clear >> u & 1u)
-        atomicMin(&tmin[slot[u]], (uint32_t)(rec[u] >> 40) & kDocMask);
-      else
-        tmin[slot[u]] = kInit;
-    }
+    for (uint32_t u = 0; u < kWPer; ++u)
+      if (u < nu) atomicMin(&tmin[slot[u]], (init >> u & 1u) ? 0u : ((uint32_t)(rec[u] >> 40) & kDocMask) + 1);
     wave_sync();
-    // phase B: probe 0 of every (document, band) is answered here; a bit whose
-    // least document is not the reader's was probed by two documents or more;
-    // the newly set bits are ORed into the words
+    // phase B: probe 0 of every (document, band) is answered here (its bit
+    // was set before document i iff tmin <= i); a clear bit whose least
+    // document is not the reader's was probed by two documents or more; the
+    // newly set bits are ORed into the words
     uint32_t owner = 0, wslot[DIRECT ? 1 : kWPer], wpend = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kWPer; ++u) {
-      if (!key1[u]) continue;
+      if (u >= nu) continue;
       const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
       const uint32_t v = tmin[slot[u]];
-      if (rec[u] & kProbe0) A.res0[(int64_t)j * A.n + i] = (v == kInit || v < i) ? 1 : 0;
-      if (!(clear >> u & 1u)) continue;
-      if (v != i) atomicOr(&tkey[slot[u]], kMulti);
+      if (rec[u] & kProbe0) A.res0[(int64_t)j * A.n + i] = v <= i ? 1 : 0;
+      const bool clr = !(init >> u & 1u);
+      atomicOr(&tkey[slot[u]], (clr && v != i + 1) ? kMulti : 0u);
       const uint32_t lb = key1[u] - 1, lw = lb >> 6;
       if (DIRECT) {
-        atomicOr(&wv[lw], 1ull << (lb & 63));
-        if (!full) atomicOr(&wk[lw >> 5], 1u << (lw & 31));
-      } else {
+        atomicOr(&wv[lw], clr ? 1ull << (lb & 63) : 0ull);
+        if (!full) atomicOr(&wk[lw >> 5], clr ? 1u << (lw & 31) : 0u);
+      } else if (clr) {
         wslot[u] = slot_of(lw, cap);
         wpend |= 1u << u;
       }
@@ -647,7 +671,7 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
       if (wpend) atomicOr(A.status, 4u);
 #pragma unroll
       for (uint32_t u = 0; u < kWPer; ++u)
-        if (clear >> u & 1u) atomicOr(&wv[wslot[u]], 1ull << ((key1[u] - 1) & 63));
+        if (u < nu && !(init >> u & 1u)) atomicOr(&wv[wslot[u]], 1ull << ((key1[u] - 1) & 63));
     }
     wave_sync();
     // changed words (this wave is their only writer in the chunk)
@@ -667,15 +691,19 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
         if (owner >> u & 1u) F[(key1[u] - 1) >> 6] = pre[u] | wv[wslot[u]];
     }
     // publish the bits a lookup can need (set before the chunk, or probed by
-    // two documents or more)
-    constexpr uint32_t kSlotsPer = kWTab / 64;
-    uint32_t ib = 0;  // this lane's table rows holding a bit to publish
+    // two documents or more), each by the record owning its slot, as
+    // (local bit + 1) << 32 | (kInit, or the least document)
+    uint32_t ib = 0;
+    unsigned long long ent[kWPer];
 #pragma unroll
-    for (uint32_t t = 0; t < kSlotsPer; ++t) {
-      const uint32_t q = t * 64 + lane;
-      if (q < cap) {
-        const uint32_t k = tkey[q];
-        if (k && (tmin[q] == kInit || (k & kMulti))) ib |= 1u << t;
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      ent[u] = 0;
+      if (own >> u & 1u) {
+        const uint32_t k = tkey[slot[u]], v = tmin[slot[u]];
+        if (v == 0 || (k & kMulti)) {
+          ib |= 1u << u;
+          ent[u] = ((unsigned long long)(k & ~kMulti) << 32) | (v == 0 ? kInit : v - 1);
+        }
       }
     }
     uint32_t mine = __popc(ib);
@@ -684,21 +712,25 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     const uint32_t room = DIRECT ? kWRegion : kWTab;
     const uint32_t pcap = min(2 * mine, room);
     wave_sync();
+    if (DIRECT) {
+      uint4 *w4 = reinterpret_cast<uint4 *>(wv);
+      const uint4 z = make_uint4(0u, 0u, 0u, 0u);
 #pragma unroll
-    for (uint32_t t = 0; t < kWTab / 64; ++t) {
-      const uint32_t q = t * 64 + lane;
-      if (q < pcap) wv[q] = 0;
+      for (uint32_t t = 0; t < kWRegion / 128; ++t) w4[t * 64 + lane] = z;
+    } else {
+#pragma unroll
+      for (uint32_t t = 0; t < kWTab / 64; ++t) {
+        const uint32_t q = t * 64 + lane;
+        if (q < pcap) wv[q] = 0;
+      }
     }
     wave_sync();
-    while (ib) {  // few per lane: about 2 x the bin's records / 64 at most
-      const uint32_t t = __ffs(ib) - 1;
-      ib &= ib - 1;
-      const uint32_t q = t * 64 + lane;
-      const uint32_t k1 = tkey[q] & ~kMulti;
-      const unsigned long long e = ((unsigned long long)k1 << 32) | tmin[q];
-      uint32_t h = slot_of(k1 - 1, pcap);
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      if (!(ib >> u & 1u)) continue;
+      uint32_t h = slot_of((uint32_t)(ent[u] >> 32) - 1, pcap);
       for (uint32_t tries = 0; tries < pcap; ++tries) {
-        if (atomicCAS(&wv[h], 0ull, e) == 0ull) break;
+        if (atomicCAS(&wv[h], 0ull, ent[u]) == 0ull) break;
         h = (h + 1 == pcap) ? 0 : h + 1;
       }
     }
