@@ -512,7 +512,8 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     uint64_t *F = A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6);
     const uint32_t cap = 2 * nr;
     const uint32_t W = (uint32_t)min((uint64_t)1 << (G.bin_bits - 6), A.words_per_band - (b0 >> 6));
-    const bool full = W == kWRegion;  // direct: every bin but the last of a band
+    // a full bin (every bin but the last of a band) is written back whole
+    const bool full = W == (1u << (G.bin_bits - 6));
     // this bin's loads first: its words (direct) or each record's word; then
     // the next bin's records
     if (DIRECT) {
@@ -540,7 +541,7 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
         }
       }
     }
-    if (DIRECT && full) {
+    if (DIRECT && W == kWRegion) {
       uint64_t reg[kWRegion / 64];
 #pragma unroll
       for (uint32_t u = 0; u < kWRegion / 64; ++u) reg[u] = F[u * 64 + lane];
@@ -558,7 +559,7 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
         const uint32_t w = u * 64 + lane;
         if (w < W) wv[w] = reg[u];
       }
-      if (lane < kWRegion / 32) wk[lane] = 0;
+      if (!full && lane < kWRegion / 32) wk[lane] = 0;
     }
     uint64_t pre[DIRECT ? 1 : kWPer];
     if (!DIRECT) {
@@ -675,10 +676,16 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     }
     wave_sync();
     // changed words (this wave is their only writer in the chunk)
-    if (DIRECT && full) {
+    if (DIRECT && W == kWRegion) {
       // all of them: nearly every 64-byte sector holds a changed word
 #pragma unroll
       for (uint32_t t = 0; t < kWRegion / 64; ++t) F[t * 64 + lane] = wv[t * 64 + lane];
+    } else if (DIRECT && full) {
+#pragma unroll
+      for (uint32_t t = 0; t < kWRegion / 64; ++t) {
+        const uint32_t w = t * 64 + lane;
+        if (w < W) F[w] = wv[w];
+      }
     } else if (DIRECT) {
 #pragma unroll
       for (uint32_t t = 0; t < kWRegion / 64; ++t) {
