@@ -15,11 +15,12 @@
 //             contiguous run;
 //   pass 2    (k_bq_part2): one block per bucket counts its bins, publishes
 //             their record ranges and splits the bucket the same way;
-//   bins      (k_bq_bin): one workgroup per bin reads the bin's filter words
+//   bins      (k_bq_bin): one wave per bin reads the bin's filter words
 //             (the state before the chunk), builds in LDS a table of its
-//             distinct bits with the least and greatest document probing
-//             each, ORs every probe into the words and writes the changed
-//             words back with plain stores (it is their only writer).  A bit
+//             distinct bits with the least document probing each and a
+//             "probed by two documents or more" flag, ORs every probe into
+//             the words and writes them back with plain stores (it is their
+//             only writer).  A bit
 //             was set before document i iff it was set before the chunk or
 //             its least document is < i.  The bin answers that at once for
 //             the probe-0 records (res0), and publishes the bits a later
@@ -361,9 +362,11 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
 // One wave per bin (64-thread workgroups), so that a bin's steps need no
 // workgroup barrier and several bins per SIMD overlap their memory latency.
 // LDS holds, per wave, the bin's distinct bits (key = local bit + 1, bit 31
-// marking "probed by two documents or more") with their least document, and
-// either the bin's filter words (direct mode) or a table of the words it
-// touches with their OR masks; that space then holds the published table.
+// marking "probed by two documents or more") with 0 for a bit set before the
+// chunk or 1 + the least document probing it, and either the bin's filter
+// words (direct mode) or a table of the words it touches with their OR masks;
+// that space then holds the published table, whose entries carry kInit or
+// the least document.
 constexpr uint32_t kWCap = 320;               // records per bin on the wave path
 constexpr uint32_t kWPer = kWCap / 64;        // records per lane
 constexpr uint32_t kWTab = 2 * kWCap;         // bit / word table slots
