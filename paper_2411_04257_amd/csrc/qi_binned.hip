@@ -757,12 +757,22 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
 }
 
 // --------------------------------------------------------------- resolve ----
-__global__ __launch_bounds__(256) void k_bq_resolve(BinnedLaunch A) {
-  const int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (i >= A.n) return;
+// A document's bands are cut into S slices (S a power of two dividing the
+// block, chosen so that a chunk of few documents still fills the device);
+// thread (slice, document) walks its slice's bands in order and stops at the
+// first match, and the slices' answers meet in LDS.
+__global__ __launch_bounds__(256) void k_bq_resolve(BinnedLaunch A, uint32_t slice_log) {
+  __shared__ uint32_t fl[kThreads];
+  const uint32_t per = kThreads >> slice_log;          // documents per block
+  const uint32_t sl = threadIdx.x / per, t = threadIdx.x - sl * per;
+  const int64_t i = (int64_t)blockIdx.x * per + t;
+  const uint32_t bps = (A.bands + (1u << slice_log) - 1) >> slice_log;  // bands per slice
+  const uint32_t j0 = sl * bps, j1 = min(A.bands, j0 + bps);
   const BinnedGeometry &G = A.G;
-  uint8_t flag = 0;
-  for (uint32_t j = 0; j < A.bands && !flag; ++j) {
+  if (threadIdx.x < per) fl[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t flag = 0;
+  for (uint32_t j = j0; i < A.n && j < j1 && !flag; ++j) {
     if (!A.res0[(int64_t)j * A.n + i]) continue;
     const uint64_t key = A.keys[(int64_t)j * A.n + i];
     const uint64_t h1 = fmix64(key ^ A.salt1), h2 = fmix64(key ^ A.salt2) | 1ull;
@@ -793,7 +803,9 @@ __global__ __launch_bounds__(256) void k_bq_resolve(BinnedLaunch A) {
     }
     if (hit) flag = 1;
   }
-  A.flags[i] = flag;
+  if (flag) atomicOr(&fl[t], 1u);
+  __syncthreads();
+  if (threadIdx.x < per && i < A.n) A.flags[i] = (uint8_t)fl[threadIdx.x];
 }
 
 inline unsigned grid1(uint64_t n, unsigned bs) {
@@ -870,7 +882,11 @@ hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_bq_bin<false>, dim3(gb), dim3(64), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_bq_resolve, dim3(grid1((uint64_t)a.n, kThreads)), dim3(kThreads), 0, s, a);
+  // slices of bands per document: enough threads for about 2^18 (document,
+  // slice) pairs, at most one band per slice and 256 slices
+  uint32_t slice_log = 0;
+  while (slice_log < 8 && ((uint64_t)a.n << slice_log) < (1ull << 18) && (1u << (slice_log + 1)) <= a.bands) ++slice_log;
+  hipLaunchKernelGGL(k_bq_resolve, dim3(grid1((uint64_t)a.n, kThreads >> slice_log)), dim3(kThreads), 0, s, a, slice_log);
   return hipGetLastError();
 }
 
