@@ -643,7 +643,7 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
       const uint32_t v = tmin[slot[u]];
       if (rec[u] & kProbe0) A.res0[(int64_t)j * A.n + i] = v <= i ? 1 : 0;
       const bool clr = !(init >> u & 1u);
-      atomicOr(&tkey[slot[u]], (clr && v != i + 1) ? kMulti : 0u);
+      if (clr && v != i + 1) atomicOr(&tkey[slot[u]], kMulti);  // rare: skipped by most rows
       const uint32_t lb = key1[u] - 1, lw = lb >> 6;
       if (DIRECT) {
         atomicOr(&wv[lw], clr ? 1ull << (lb & 63) : 0ull);
