@@ -1,7 +1,8 @@
 """LSHBloom CPU oracle (test infrastructure only).
 
 A plain sequential reference of the LSHBloom hot path, written in C
-(`lshbloom_oracle.c`) and wrapped here with ctypes.  Only the tests, the smoke
+(`lshbloom_oracle.c`) and wrapped here with ctypes, and of the exact
+MinHashLSH band index it replaces (`exact_lsh.py`, plain Python).  Only the tests, the smoke
 check and the benchmark's CPU-baseline leg may import it; the GPU library never
 does, and the two share no code.
 """
@@ -26,3 +27,4 @@ from .oracle import (  # noqa: F401
     shingle_hash,
     splitmix64_stream,
 )
+from .exact_lsh import ExactLSHOracle, brute_force_flags  # noqa: F401,E402

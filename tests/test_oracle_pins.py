@@ -412,3 +412,57 @@ def test_fidelity_on_brute_force_jaccard():
     if mid.sum() >= 10:
         want = np.mean(1 - (1 - maxJ[mid] ** 8) ** 16)
         assert abs(flags[mid].mean() - want) < 0.35
+
+
+# ------------------------------------------- exact MinHashLSH reference ----
+
+def _planted_sigs(n, num_perm, bands, rows, seed):
+    """Random signatures with band repeats (synth's counter-based generator)
+    and a few whole repeated documents."""
+    from paper_2411_04257_amd import synth
+
+    s = synth.signature_batch(0, n, num_perm, bands, rows, n, 0.3, 0.5, seed).numpy().view(np.uint32).copy()
+    rng = np.random.default_rng(seed)
+    for i in rng.choice(np.arange(1, n), size=max(1, n // 50), replace=False):
+        s[i] = s[rng.integers(0, i)]
+    return s
+
+
+@pytest.mark.parametrize("bands,rows,num_perm", [(16, 8, 128), (5, 3, 16), (1, 4, 4)])
+def test_exact_oracle_matches_brute_force(bands, rows, num_perm):
+    """The streaming band index against every pair compared band by band
+    (Section 2's candidate-pair definition), over calls of uneven sizes
+    (including an empty one): the flags do not depend on the split."""
+    from oracle.exact_lsh import ExactLSHOracle, brute_force_flags
+
+    s = _planted_sigs(240, num_perm, bands, rows, seed=11 + bands)
+    o = ExactLSHOracle(num_perm, bands, rows)
+    got = np.concatenate([o.query_insert(s[a:b]) for a, b in [(0, 1), (1, 1), (1, 70), (70, 71), (71, 240)]])
+    want = brute_force_flags(s, bands, rows)
+    assert got.tolist() == want.tolist()
+    assert 20 < want.sum() < 240
+    assert o.docs_inserted == 240
+
+
+def test_exact_oracle_without_repeats_flags_nothing():
+    from oracle.exact_lsh import ExactLSHOracle
+
+    rng = np.random.default_rng(5)
+    s = rng.integers(0, 2**32, size=(2000, 128), dtype=np.uint64).astype(np.uint32)
+    assert ExactLSHOracle(128, 16, 8).query_insert(s).sum() == 0
+
+
+def test_exact_oracle_contained_in_bloom_oracle():
+    """Exact band match implies the same band key and so the same Bloom
+    bits: LSHBloom's flags contain MinHashLSH's (Section 3.2); the excess
+    stays within the Bloom false-positive budget."""
+    from oracle.exact_lsh import ExactLSHOracle
+
+    s = _planted_sigs(3000, 128, 16, 8, seed=3)
+    ex = ExactLSHOracle(128, 16, 8).query_insert(s)
+    idx = oracle.OracleIndex(128, 16, 8, 3000, 1e-5, seed=42)
+    bl = idx.query_insert(s)
+    idx.close()
+    assert (bl >= ex).all()
+    assert ex.sum() > 500
+    assert bl.sum() - ex.sum() <= 3
