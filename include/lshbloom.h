@@ -276,6 +276,44 @@ int lshbloom_pipeline_info(const lshbloom_pipeline_t *pl, lshbloom_pipeline_info
 /* Finish outstanding batches (delivering their flags) and free the pipeline. */
 void lshbloom_pipeline_destroy(lshbloom_pipeline_t *pl);
 
+/* ---- Exact MinHashLSH band index (the comparison baseline) ----------------
+ *
+ * The traditional index that LSHBloom replaces (Section 2, "MinHashLSH for
+ * Text Deduplication"; Section 3): per band, a hash table keyed by the band's
+ * r signature values, compared exactly.  Document i is flagged iff, for some
+ * band j, its r values of band j equal those of an earlier document (of an
+ * earlier call, or 0..i-1 of this call); every document is then inserted.
+ * On the same stream LSHBloom's flags contain these flags (equal band values
+ * give equal band keys); the difference is the Bloom filters' false positives
+ * and band-key collisions (Section 3.2).  Device memory, allocated by create:
+ * per band 2^ceil(log2(2 capacity)) slots of 12 + 4 r bytes. */
+typedef struct lshbloom_exact lshbloom_exact_t;
+
+/* capacity_docs: documents the index can hold over its life, 1..2^30 (a call
+ * that would exceed it returns LSHBLOOM_EINVAL with nothing launched).
+ * fp_bits: bits of the 64-bit fingerprint of a band's values that pick its
+ * slot and prefilter comparisons (0 = 64); fewer bits only make different
+ * values share fingerprints more often, which stays exact but slower (for
+ * tests).  NULL on error (message in lshbloom_last_error). */
+lshbloom_exact_t *lshbloom_exact_create(uint32_t num_perm, uint32_t bands, uint32_t rows, uint64_t capacity_docs,
+                                        uint32_t fp_bits);
+
+/* Frees the tables after the index's outstanding work.  NULL is a no-op. */
+void lshbloom_exact_destroy(lshbloom_exact_t *x);
+
+/* Query then insert in stream order, as lshbloom_query_insert: d_sigs uint32
+ * [n_docs][num_perm] and d_flags uint8 [n_docs] are device pointers owned by
+ * the caller; asynchronous on stream; calls on one index are ordered by host
+ * call order.  n_docs = 0 is a no-op. */
+int lshbloom_exact_query_insert(lshbloom_exact_t *x, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags,
+                                lshbloom_stream_t stream);
+
+/* Host outputs (each may be NULL): documents inserted, bytes of the tables,
+ * and the number of (document, band) pairs so far whose fingerprint was
+ * shared with different band values (placed exactly by full comparison).
+ * Synchronous when fp_shared is requested. */
+int lshbloom_exact_stats(lshbloom_exact_t *x, uint64_t *docs_inserted, uint64_t *table_bytes, uint64_t *fp_shared);
+
 /* Message for the calling thread's last failure ("" if none). */
 const char *lshbloom_last_error(void);
 

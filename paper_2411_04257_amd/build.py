@@ -8,7 +8,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblshbloom.so")
-SOURCES = ["kernels.hip", "qi_binned.hip", "lshbloom_api.hip", "pipeline.hip"]
+SOURCES = ["kernels.hip", "qi_binned.hip", "lshbloom_api.hip", "pipeline.hip", "exact_lsh.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -100,6 +100,7 @@ EXPORTS = [
     "lshbloom_count_set_bits", "lshbloom_save", "lshbloom_load", "lshbloom_info", "lshbloom_p_band_from_eff", "lshbloom_optimal_bands", "lshbloom_last_error",
     "lshbloom_pipeline_create", "lshbloom_pipeline_submit", "lshbloom_pipeline_wait", "lshbloom_pipeline_poll",
     "lshbloom_pipeline_info", "lshbloom_pipeline_destroy",
+    "lshbloom_exact_create", "lshbloom_exact_destroy", "lshbloom_exact_query_insert", "lshbloom_exact_stats",
 ]
 
 _lib = None
@@ -147,6 +148,14 @@ def load(path: str = LIB_PATH):
     L.lshbloom_pipeline_info.restype = ctypes.c_int
     L.lshbloom_pipeline_destroy.argtypes = [vp]
     L.lshbloom_pipeline_destroy.restype = None
+    L.lshbloom_exact_create.argtypes = [u32, u32, u32, u64, u32]
+    L.lshbloom_exact_create.restype = vp
+    L.lshbloom_exact_destroy.argtypes = [vp]
+    L.lshbloom_exact_destroy.restype = None
+    L.lshbloom_exact_query_insert.argtypes = [vp, vp, i64, vp, vp]
+    L.lshbloom_exact_query_insert.restype = ctypes.c_int
+    L.lshbloom_exact_stats.argtypes = [vp, vp, vp, vp]
+    L.lshbloom_exact_stats.restype = ctypes.c_int
     L.lshbloom_last_error.argtypes = []
     L.lshbloom_last_error.restype = ctypes.c_char_p
     for name in ("lshbloom_minhash", "lshbloom_query_insert", "lshbloom_query", "lshbloom_insert",
@@ -392,3 +401,48 @@ class Pipeline:
             self.close()
         except Exception:
             pass
+
+
+class ExactLSH:
+    """The exact MinHashLSH band index (the comparison baseline) on the
+    current GPU: per band a table keyed by the band's r values."""
+
+    def __init__(self, num_perm: int, bands: int, rows: int, capacity_docs: int, fp_bits: int = 0):
+        L = load()
+        self._x = L.lshbloom_exact_create(num_perm, bands, rows, int(capacity_docs), int(fp_bits))
+        if not self._x:
+            raise LSHBloomError(EINVAL, last_error())
+        self.num_perm, self.bands, self.rows = num_perm, bands, rows
+
+    def query_insert(self, sigs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        if sigs.dim() != 2 or sigs.shape[1] != self.num_perm:
+            raise ValueError("sigs must have shape [n_docs, num_perm]")
+        n = sigs.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=sigs.device)
+        if n:
+            _check(load().lshbloom_exact_query_insert(self._x, _dev_ptr(sigs, _U32, "sigs"), n,
+                                                      _dev_ptr(out, (torch.uint8,), "out"), _stream()))
+        return out
+
+    def stats(self) -> dict:
+        d, t, f = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(load().lshbloom_exact_stats(self._x, ctypes.byref(d), ctypes.byref(t), ctypes.byref(f)))
+        return {"docs_inserted": d.value, "table_bytes": t.value, "fp_shared": f.value}
+
+    def close(self):
+        if getattr(self, "_x", None):
+            load().lshbloom_exact_destroy(self._x)
+            self._x = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

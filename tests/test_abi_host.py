@@ -65,6 +65,19 @@ def test_null_handle_calls_fail_cleanly(lib):
     assert lib.lshbloom_save(None, b"x", None) == -1
     assert lib.lshbloom_load(None, b"x", None) == -1
     lib.lshbloom_destroy(None)
+    assert lib.lshbloom_exact_query_insert(None, None, 0, None, None) == -1
+    assert lib.lshbloom_exact_stats(None, None, None, None) == -1
+    lib.lshbloom_exact_destroy(None)
+
+
+def test_exact_index_rejects_bad_parameters_without_device(lib):
+    from paper_2411_04257_amd import lshbloom
+
+    for args, needle in [((128, 17, 8, 1000, 0), "bands * rows"), ((128, 0, 8, 1000, 0), "bands"),
+                         ((128, 16, 8, 0, 0), "capacity"), ((128, 16, 8, (1 << 30) + 1, 0), "capacity"),
+                         ((128, 16, 8, 1000, 65), "fp_bits"), ((1024, 16, 8, 1000, 0), "num_perm")]:
+        assert lib.lshbloom_exact_create(*args) is None
+        assert needle in lshbloom.last_error(), (args, lshbloom.last_error())
 
 
 def test_p_band_from_eff_matches_section_4_3():
