@@ -53,10 +53,11 @@ def parse():
     ap.add_argument("--cpu-sample-docs", type=int, default=3072)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--qi-mode", type=int, default=0, help="0 automatic, 1 direct, 2 binned query-insert")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched"],
+    ap.add_argument("--form", default="plain", choices=["plain", "batched", "fidelity"],
                     help="plain: per-batch calls on HBM-resident inputs; batched: the host-to-host pipeline "
                          "(length buckets, overlapping slots, hipGraph, autotuner) compared with per-batch "
-                         "calls that copy the same host batches")
+                         "calls that copy the same host batches; fidelity: LSHBloom against the exact "
+                         "MinHashLSH band index on the same signatures, scored on the corpus's near-dup labels")
     ap.add_argument("--batch", type=int, default=None,
                     help="documents per batch (default: the workload's; c3 leaves it open)")
     ap.add_argument("--chunk-docs", type=int, default=None,
@@ -295,6 +296,88 @@ def run_batched(args, wl, torch, np, lshbloom, synth, dev):
     return res, None, None
 
 
+def _scores(flags, truth):
+    tp = int((flags & truth).sum())
+    fp = int((flags & ~truth).sum())
+    fn = int((~flags & truth).sum())
+    prec = tp / (tp + fp) if tp + fp else 1.0
+    rec = tp / (tp + fn) if tp + fn else 1.0
+    f1 = 2 * prec * rec / (prec + rec) if prec + rec else 0.0
+    return {"flagged": int(flags.sum()), "tp": tp, "fp": fp, "fn": fn, "precision": prec, "recall": rec, "f1": f1}
+
+
+def _recall_by_j(np, target_j, truth, fb, fe):
+    """Recall of each index per band of the generator's target Jaccard."""
+    out = []
+    for lo, hi in [(0.6, 0.7), (0.7, 0.8), (0.8, 0.9), (0.9, 0.951)]:
+        sel = truth & (target_j >= lo) & (target_j < hi)
+        k = int(sel.sum())
+        out.append({"target_j": [lo, min(hi, 0.95)], "near_dups": k,
+                    "lshbloom": float(fb[sel].mean()) if k else None, "exact": float(fe[sel].mean()) if k else None})
+    return out
+
+
+def run_fidelity(args, wl, torch, np, lshbloom, synth, dev):
+    """LSHBloom against the exact MinHashLSH band index (Section 2's index,
+    which LSHBloom replaces) on the same GPU signatures of a labelled corpus:
+    precision, recall and F1 of each against the generator's near-duplicate
+    labels (a document is a near-duplicate iff it was made from an earlier
+    one), the documents only LSHBloom flags, and each index's query-insert
+    time and size."""
+    B = wl.batch
+    n_batches = args.warmup + args.steps
+    if B * n_batches > wl.n_docs:
+        print(f"warmup + steps exceed the {wl.n_docs // B} full batches of the corpus", file=sys.stderr)
+        sys.exit(2)
+    n = B * n_batches
+    t_gen = time.perf_counter()
+    corpus = synth.make_corpus(wl, device=dev, n_docs=n)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t_gen
+    truth = np.asarray(corpus.is_dup[:n]).astype(bool)
+
+    idx = _index(args, wl, lshbloom)
+    ex = lshbloom.ExactLSH(wl.num_perm, wl.bands, wl.rows, capacity_docs=n)
+    sigs = torch.empty((B, wl.num_perm), dtype=torch.int32, device=dev)
+    fb = torch.empty((n_batches, B), dtype=torch.uint8, device=dev)
+    fe = torch.empty((n_batches, B), dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    ev = _events(n_batches)
+    for b in range(n_batches):
+        idx.minhash(corpus.offsets[b * B:(b + 1) * B + 1], corpus.tokens, out=sigs)
+        ev[b][0].record(stream)
+        idx.query_insert(sigs, out=fb[b])
+        ev[b][1].record(stream)
+        ex.query_insert(sigs, out=fe[b])
+        ev[b][2].record(stream)
+    torch.cuda.synchronize()
+    timed = range(args.warmup, n_batches)
+    bloom_ms = float(np.mean([ev[b][0].elapsed_time(ev[b][1]) for b in timed]))
+    exact_ms = float(np.mean([ev[b][1].elapsed_time(ev[b][2]) for b in timed]))
+    fb_h = fb.cpu().numpy().reshape(-1).astype(bool)
+    fe_h = fe.cpu().numpy().reshape(-1).astype(bool)
+    sb, se = _scores(fb_h, truth), _scores(fe_h, truth)
+    inf = idx.info()
+    bloom_bytes = inf["m_bits"] // 8 * wl.bands
+    st = ex.stats()
+    res = {
+        "value": sb["f1"] - se["f1"],
+        "ms_per_step": bloom_ms,
+        "docs_timed": args.steps * B,
+        "labelled_near_dups": int(truth.sum()),
+        "lshbloom": dict(sb, qi_ms_per_batch=bloom_ms, docs_per_s=B / (bloom_ms * 1e-3), index_bytes=bloom_bytes),
+        "exact_minhashlsh": dict(se, qi_ms_per_batch=exact_ms, docs_per_s=B / (exact_ms * 1e-3),
+                                 index_bytes=st["table_bytes"], fingerprints_shared=st["fp_shared"]),
+        "recall_by_target_jaccard": _recall_by_j(np, corpus.target_j[:n], truth, fb_h, fe_h),
+        "exact_flags_missing_from_lshbloom": int((fe_h & ~fb_h).sum()),
+        "lshbloom_only_flags": int((fb_h & ~fe_h).sum()),
+        "index_size_ratio": st["table_bytes"] / bloom_bytes,
+        "corpus_gen_s": t_gen,
+    }
+    ex.close()
+    return res, None, None
+
+
 def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
     """Filter-scale query-insert: batches of precomputed signatures only."""
     B = wl.batch
@@ -515,6 +598,10 @@ def main():
         metric = "p99 serve latency (ms) at the highest offered load, continuous batching"
         unit = "ms"
         higher = False
+    elif args.form == "fidelity":
+        res, corpus, idx = run_fidelity(args, wl, torch, np, lshbloom, synth, dev)
+        metric = "F1 gap, LSHBloom minus exact MinHashLSH, on the same signatures (near-dup labels)"
+        unit = "F1"
     elif args.form == "batched":
         res, corpus, idx = run_batched(args, wl, torch, np, lshbloom, synth, dev)
         metric = "docs/sec end-to-end (MinHash+band Bloom), bit-exact flags"
