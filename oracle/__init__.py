@@ -11,17 +11,20 @@ from .oracle import (  # noqa: F401
     P61,
     OracleIndex,
     band_key,
+    band_key61,
     build,
     fmix64,
     fn_lsh,
     fp_lsh,
     lib,
     minhash_doc,
+    minhash_doc61,
     optimal_br,
     p_band_from_eff,
     p_eff_from_band,
     params,
     perm,
+    perm61,
     positions,
     sha1,
     shingle_hash,

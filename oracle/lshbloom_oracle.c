@@ -429,6 +429,92 @@ void ora_band_keys(const ora_index *h, const uint32_t *sigs, int64_t n_docs, uin
       keys[(uint64_t)i * h->bands + j] = ora_band_key(sigs + (uint64_t)i * h->num_perm, j, h->rows, h->salt_m);
 }
 
+/* ------------------------------------------------------------------------ */
+/* Wide-value variant (§4.5: the index size does not depend on the width of  */
+/* the MinHash values, so they may be widened at no cost in index space).    */
+/* The permutation value is kept whole, h_i(x) = (a_i x + b_i) mod (2^61-1), */
+/* 61 bits, instead of its low 32 bits; the shingle hash x is unchanged.     */
+/* ------------------------------------------------------------------------ */
+uint64_t ora_perm61(uint64_t a, uint64_t b, uint32_t x) {
+  u128 v = (u128)a * (u128)x + (u128)b;
+  return (uint64_t)(v % (u128)ORA_P61);
+}
+
+/* Wide signature of one document: sig[i] = min over the shingle set of
+   h_i; the empty set gives all ones (2^64 - 1, above every value). */
+void ora_minhash_doc61(const uint32_t *tok, int64_t L, uint32_t w, uint32_t num_perm,
+                       const uint64_t *a, const uint64_t *b, uint64_t *sig) {
+  for (uint32_t i = 0; i < num_perm; ++i) sig[i] = ~0ull;
+  if (L <= 0) return;
+  int64_t n_sh = L >= (int64_t)w ? L - (int64_t)w + 1 : 1;
+  uint32_t sh_len = L >= (int64_t)w ? w : (uint32_t)L;
+  for (int64_t t = 0; t < n_sh; ++t) {
+    uint32_t x = ora_shingle_hash(tok + t, sh_len);
+    for (uint32_t i = 0; i < num_perm; ++i) {
+      uint64_t v = ora_perm61(a[i], b[i], x);
+      if (v < sig[i]) sig[i] = v;
+    }
+  }
+}
+
+int ora_minhash61(const ora_index *h, const int64_t *offsets, const uint32_t *tokens, int64_t n_docs,
+                  uint64_t *sigs) {
+  if (n_docs < 0) return -1;
+  for (int64_t d = 0; d < n_docs; ++d) {
+    if (offsets[d + 1] < offsets[d]) return -1;
+    ora_minhash_doc61(tokens + offsets[d], offsets[d + 1] - offsets[d], h->w, h->num_perm, h->a, h->b,
+                      sigs + (uint64_t)d * h->num_perm);
+  }
+  return 0;
+}
+
+/* Band key of a band of wide values (§4.1, band hash equation): the same sum
+   mod 2^64 of per-row finalizer terms; the value fills the word, so the row
+   index enters as an offset of t times the golden-ratio constant before the
+   salt: term = fmix64((v + t * 0x9E3779B97F4A7C15) xor salt_M). */
+uint64_t ora_band_key61(const uint64_t *sig, uint32_t band, uint32_t rows, uint64_t salt_m) {
+  uint64_t K = 0;
+  for (uint32_t t = 0; t < rows; ++t) {
+    uint64_t v = sig[(uint64_t)band * rows + t] + (uint64_t)t * 0x9E3779B97F4A7C15ull;
+    K += ora_fmix64(v ^ salt_m);
+  }
+  return K;
+}
+
+void ora_band_keys61(const ora_index *h, const uint64_t *sigs, int64_t n_docs, uint64_t *keys) {
+  for (int64_t i = 0; i < n_docs; ++i)
+    for (uint32_t j = 0; j < h->bands; ++j)
+      keys[(uint64_t)i * h->bands + j] = ora_band_key61(sigs + (uint64_t)i * h->num_perm, j, h->rows, h->salt_m);
+}
+
+/* Stream query-then-insert from band keys [n_docs][bands] (§4.1 reduces
+   each band to one integer; from there on the steps are those of
+   ora_query_insert). */
+int ora_query_insert_keys(ora_index *h, const uint64_t *keys, int64_t n_docs, uint8_t *flags) {
+  if (n_docs < 0) return -1;
+  uint64_t *g = (uint64_t *)malloc(sizeof(uint64_t) * h->k);
+  if (!g) return -1;
+  for (int64_t i = 0; i < n_docs; ++i) {
+    const uint64_t *K = keys + (uint64_t)i * h->bands;
+    int hit = 0;
+    for (uint32_t j = 0; j < h->bands; ++j) {
+      ora_positions(K[j], h->salt1, h->salt2, h->m_bits, h->k, g);
+      int all = 1;
+      for (uint32_t l = 0; l < h->k; ++l)
+        if (!ora_test_bit(h, j, g[l])) all = 0;
+      if (all) hit = 1;
+    }
+    flags[i] = (uint8_t)hit;
+    for (uint32_t j = 0; j < h->bands; ++j) {
+      ora_positions(K[j], h->salt1, h->salt2, h->m_bits, h->k, g);
+      for (uint32_t l = 0; l < h->k; ++l) ora_set_bit(h, j, g[l]);
+    }
+    h->docs_inserted += 1;
+  }
+  free(g);
+  return 0;
+}
+
 /* Accessors for tests. */
 uint64_t ora_m_bits(const ora_index *h) { return h->m_bits; }
 uint32_t ora_k(const ora_index *h) { return h->k; }

@@ -72,6 +72,16 @@ def lib():
         L.ora_destroy.argtypes = [ctypes.c_void_p]
         L.ora_minhash.argtypes = [ctypes.c_void_p, _i64p, _u32p, ctypes.c_int64, _u32p]
         L.ora_minhash.restype = ctypes.c_int
+        L.ora_perm61.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]
+        L.ora_perm61.restype = ctypes.c_uint64
+        L.ora_minhash_doc61.argtypes = [_u32p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, _u64p, _u64p, _u64p]
+        L.ora_minhash61.argtypes = [ctypes.c_void_p, _i64p, _u32p, ctypes.c_int64, _u64p]
+        L.ora_minhash61.restype = ctypes.c_int
+        L.ora_band_key61.argtypes = [_u64p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64]
+        L.ora_band_key61.restype = ctypes.c_uint64
+        L.ora_band_keys61.argtypes = [ctypes.c_void_p, _u64p, ctypes.c_int64, _u64p]
+        L.ora_query_insert_keys.argtypes = [ctypes.c_void_p, _u64p, ctypes.c_int64, _u8p]
+        L.ora_query_insert_keys.restype = ctypes.c_int
         L.ora_query_insert.argtypes = [ctypes.c_void_p, _u32p, ctypes.c_int64, _u8p]
         L.ora_query_insert.restype = ctypes.c_int
         L.ora_query.argtypes = [ctypes.c_void_p, _u32p, ctypes.c_int64, _u8p]
@@ -120,6 +130,26 @@ def splitmix64_stream(seed: int, n: int) -> list[int]:
 
 def perm(a: int, b: int, x: int) -> int:
     return int(lib().ora_perm(a, b, x))
+
+
+def perm61(a: int, b: int, x: int) -> int:
+    return int(lib().ora_perm61(a, b, x))
+
+
+def minhash_doc61(tokens, w: int, a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    tok = np.ascontiguousarray(tokens, dtype=np.uint32)
+    a = np.ascontiguousarray(a, dtype=np.uint64)
+    b = np.ascontiguousarray(b, dtype=np.uint64)
+    sig = np.zeros(len(a), np.uint64)
+    tp = _ptr(tok, ctypes.c_uint32) if len(tok) else _ptr(np.zeros(1, np.uint32), ctypes.c_uint32)
+    lib().ora_minhash_doc61(tp, len(tok), w, len(a), _ptr(a, ctypes.c_uint64), _ptr(b, ctypes.c_uint64),
+                            _ptr(sig, ctypes.c_uint64))
+    return sig
+
+
+def band_key61(sig: np.ndarray, band: int, rows: int, salt_m: int) -> int:
+    sig = np.ascontiguousarray(sig, dtype=np.uint64)
+    return int(lib().ora_band_key61(_ptr(sig, ctypes.c_uint64), band, rows, salt_m))
 
 
 def minhash_doc(tokens, w: int, a: np.ndarray, b: np.ndarray) -> np.ndarray:
@@ -242,6 +272,32 @@ class OracleIndex:
         if len(sigs):
             lib().ora_band_keys(self._h, _ptr(sigs, ctypes.c_uint32), len(sigs), _ptr(keys, ctypes.c_uint64))
         return keys
+
+    # -- wide-value variant (61-bit signature values) ------------------------
+    def minhash61(self, offsets: np.ndarray, tokens: np.ndarray) -> np.ndarray:
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        tokens = np.ascontiguousarray(tokens, dtype=np.uint32)
+        n = len(offsets) - 1
+        sigs = np.zeros((max(n, 0), self.num_perm), np.uint64)
+        tp = _ptr(tokens, ctypes.c_uint32) if len(tokens) else _ptr(np.zeros(1, np.uint32), ctypes.c_uint32)
+        rc = lib().ora_minhash61(self._h, _ptr(offsets, ctypes.c_int64), tp, n, _ptr(sigs, ctypes.c_uint64))
+        if rc != 0:
+            raise ValueError("bad CSR batch")
+        return sigs
+
+    def band_keys61(self, sigs: np.ndarray) -> np.ndarray:
+        sigs = np.ascontiguousarray(sigs, dtype=np.uint64).reshape(-1, self.num_perm)
+        keys = np.zeros((len(sigs), self.bands), np.uint64)
+        if len(sigs):
+            lib().ora_band_keys61(self._h, _ptr(sigs, ctypes.c_uint64), len(sigs), _ptr(keys, ctypes.c_uint64))
+        return keys
+
+    def query_insert_keys(self, keys: np.ndarray) -> np.ndarray:
+        keys = np.ascontiguousarray(keys, dtype=np.uint64).reshape(-1, self.bands)
+        flags = np.zeros(len(keys), np.uint8)
+        if len(keys):
+            lib().ora_query_insert_keys(self._h, _ptr(keys, ctypes.c_uint64), len(keys), _ptr(flags, ctypes.c_uint8))
+        return flags
 
     def filters(self) -> np.ndarray:
         """A copy of the filter words, shape [bands, words_per_band]."""

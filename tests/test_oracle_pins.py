@@ -466,3 +466,118 @@ def test_exact_oracle_contained_in_bloom_oracle():
     assert (bl >= ex).all()
     assert ex.sum() > 500
     assert bl.sum() - ex.sum() <= 3
+
+
+# ------------------------------------------- wide-value (61-bit) variant ----
+
+def _brute_sig61(tokens, w, a, b):
+    tokens = [int(t) for t in tokens]
+    L = len(tokens)
+    if L == 0:
+        return [2**64 - 1] * len(a)
+    shingles = {tuple(tokens[t:t + w]) for t in range(L - w + 1)} if L >= w else {tuple(tokens)}
+    xs = [struct.unpack("<I", hashlib.sha1(struct.pack("<%dI" % len(s), *s)).digest()[:4])[0] for s in shingles]
+    return [min((int(ai) * x + int(bi)) % P61 for x in xs) for ai, bi in zip(a, b)]
+
+
+def test_perm61_matches_big_integers():
+    rng = np.random.default_rng(12)
+    cases = [(1, 0, 0), (P61 - 1, P61 - 1, 2**32 - 1), (1, P61 - 1, 1), (1, P61 - 2, 1), (2**61 - 2, 2**61 - 2, 1)]
+    for _ in range(20000):
+        cases.append((int(rng.integers(1, P61)), int(rng.integers(0, P61)), int(rng.integers(0, 2**32))))
+    for a, b, x in cases:
+        assert oracle.perm61(a, b, x) == (a * x + b) % P61, (a, b, x)
+
+
+def test_minhash61_is_min_over_the_shingle_set():
+    """Section 4.5's wider values: the untruncated permutation value's
+    minimum over the shingle set (hashlib SHA-1, Python big integers)."""
+    idx = oracle.OracleIndex(16, 4, 4, 1000, 1e-3, seed=99)
+    a, b, _ = idx.coeffs()
+    rng = np.random.default_rng(6)
+    for L in [0, 1, 2, 4, 5, 6, 9, 40, 120]:
+        tok = rng.integers(0, 3, L).astype(np.uint32)
+        sig = oracle.minhash_doc61(tok, 5, a, b)
+        assert [int(v) for v in sig] == _brute_sig61(tok, 5, a, b), L
+    # the batch entry point agrees with the per-document one
+    off = np.array([0, 0, 3, 40, 41], np.int64)
+    tok = rng.integers(0, 1000, 41).astype(np.uint32)
+    sigs = idx.minhash61(off, tok)
+    for d in range(4):
+        assert sigs[d].tolist() == oracle.minhash_doc61(tok[off[d]:off[d + 1]], 5, a, b).tolist()
+
+
+def test_minhash61_estimator_binomial_bound():
+    P = 128
+    idx = oracle.OracleIndex(P, 16, 8, 1000, 1e-3, seed=77)
+    a, b, _ = idx.coeffs()
+    rng = np.random.default_rng(2)
+    zs = []
+    for _ in range(200):
+        shared = int(rng.integers(0, 61))
+        A, B = _disjoint_pair(rng, 60, shared)
+        J = _jaccard(A, B)
+        Jh = float(np.mean(oracle.minhash_doc61(A, 5, a, b) == oracle.minhash_doc61(B, 5, a, b)))
+        sd = math.sqrt(max(J * (1 - J), 1e-12) / P)
+        zs.append(abs(Jh - J) / sd if 0 < J < 1 else (0.0 if Jh == J else 99.0))
+    assert np.mean(np.array(zs) <= 4.0) >= 0.99
+
+
+def test_band_key61_properties():
+    """Equal bands give equal keys; a key is a sum of per-row terms (the
+    change from replacing one row's value does not depend on the other
+    rows); rows are told apart by position; no collisions among 2e5 random
+    bands."""
+    salt = 0x1234_5678_9ABC_DEF0
+    rng = np.random.default_rng(9)
+    r = 8
+    A = rng.integers(0, P61, r, dtype=np.uint64)
+    assert oracle.band_key61(A, 0, r, salt) == oracle.band_key61(A.copy(), 0, r, salt)
+    for t in range(r):
+        u = np.uint64(rng.integers(0, P61))
+        ctx2 = rng.integers(0, P61, r, dtype=np.uint64)
+        A2, C2 = A.copy(), ctx2.copy()
+        A2[t] = u
+        C2[t] = A[t]
+        C3 = C2.copy()
+        C3[t] = u
+        d1 = (oracle.band_key61(A2, 0, r, salt) - oracle.band_key61(A, 0, r, salt)) % 2**64
+        d2 = (oracle.band_key61(C3, 0, r, salt) - oracle.band_key61(C2, 0, r, salt)) % 2**64
+        assert d1 == d2 != 0, t
+    swapped = A.copy()
+    swapped[[0, 1]] = swapped[[1, 0]]
+    assert oracle.band_key61(swapped, 0, r, salt) != oracle.band_key61(A, 0, r, salt)
+    idx = oracle.OracleIndex(64, 8, 8, 1000, 1e-3, seed=5)
+    sigs = rng.integers(0, P61, size=(25000, 64), dtype=np.uint64)
+    keys = idx.band_keys61(sigs)
+    assert len(np.unique(keys)) == keys.size
+    assert keys[3, 2] == oracle.band_key61(sigs[3], 2, 8, idx.coeffs()[2][0])
+
+
+def test_query_insert_from_keys_equals_query_insert():
+    """The band key is the whole interface between MinHash and the Bloom
+    index (Section 4.1): inserting the keys of the signatures gives the same
+    flags and filters as inserting the signatures."""
+    from paper_2411_04257_amd import synth
+
+    s = synth.signature_batch(0, 3000, 128, 16, 8, 3000, 0.3, 0.5, 21).numpy().view(np.uint32)
+    i1 = oracle.OracleIndex(128, 16, 8, 3000, 1e-4, seed=42)
+    i2 = oracle.OracleIndex(128, 16, 8, 3000, 1e-4, seed=42)
+    f1 = i1.query_insert(s)
+    f2 = np.concatenate([i2.query_insert_keys(i2.band_keys(s[:1000])), i2.query_insert_keys(i2.band_keys(s[1000:]))])
+    assert f1.tolist() == f2.tolist() and f1.sum() > 300
+    assert (i1.filters() == i2.filters()).all()
+
+
+def test_wide_pipeline_flags_repeats():
+    """The wide variant end to end (MinHash of 61-bit values, their band
+    keys, query-insert from keys): exact repeats are flagged, fresh random
+    documents are not."""
+    idx = oracle.OracleIndex(128, 16, 8, 400, 1e-6, seed=42)
+    rng = np.random.default_rng(4)
+    docs = [rng.integers(0, 50000, int(rng.integers(20, 200))).astype(np.uint32) for _ in range(200)]
+    docs += [docs[i] for i in range(0, 200, 10)]
+    off = np.concatenate([[0], np.cumsum([len(d) for d in docs])]).astype(np.int64)
+    tok = np.concatenate(docs)
+    flags = idx.query_insert_keys(idx.band_keys61(idx.minhash61(off, tok)))
+    assert flags[:200].sum() == 0 and flags[200:].all()
