@@ -166,6 +166,29 @@ int lshbloom_query(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, uint8_
 /* Insert only (Section 4.1): set every band's bits of every document. */
 int lshbloom_insert(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, lshbloom_stream_t stream);
 
+/* Query then insert from band keys (Section 4.1 reduces each band of a
+ * signature to one integer, the key; the filters see only keys):
+ *   d_keys:  uint64 [n_docs][bands], e.g. lshbloom_band_keys or
+ *            lshbloom_band_keys61 output.
+ *   d_flags: uint8 [n_docs] output.
+ * Same order, ordering and errors as lshbloom_query_insert, which equals
+ * this call on lshbloom_band_keys of its signatures. */
+int lshbloom_query_insert_keys(lshbloom_t *h, const uint64_t *d_keys, int64_t n_docs, uint8_t *d_flags,
+                               lshbloom_stream_t stream);
+
+/* Wide-value MinHash (Section 4.5: the index size does not depend on the
+ * width of the MinHash values): d_sigs uint64 [n_docs][num_perm], each value
+ * the whole permutation value (a_i x + b_i) mod (2^61 - 1) minimised over the
+ * document's shingles (x the same 32-bit shingle hash); an empty document
+ * gives 2^64 - 1 throughout.  Same CSR input and ordering as lshbloom_minhash. */
+int lshbloom_minhash61(lshbloom_t *h, const int64_t *d_offsets, const uint32_t *d_tokens, int64_t n_docs,
+                       uint64_t *d_sigs, lshbloom_stream_t stream);
+
+/* Band keys of wide signatures, uint64 [n_docs][bands]: per band the sum
+ * mod 2^64 over its rows t of fmix64((v + t * 0x9E3779B97F4A7C15) ^ salt_M). */
+int lshbloom_band_keys61(lshbloom_t *h, const uint64_t *d_sigs, int64_t n_docs, uint64_t *d_keys,
+                         lshbloom_stream_t stream);
+
 /* Band keys K_j of each document (Section 4.1), uint64 [n_docs][bands]. */
 int lshbloom_band_keys(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, uint64_t *d_keys,
                        lshbloom_stream_t stream);

@@ -255,6 +255,15 @@ LB_FN uint32_t shingle_hash_var(const uint32_t *tok, uint32_t len) {
   return sha1_block_h0_le(W);
 }
 
+// Band key of one band of wide (61-bit) values: sum over its r rows of
+// fmix64((v + t * 0x9E3779B97F4A7C15) ^ salt); the row enters as an offset
+// since the value fills the word.
+LB_FN uint64_t band_key61(const uint64_t *row0, uint32_t rows, uint64_t salt_m) {
+  uint64_t K = 0;
+  for (uint32_t t = 0; t < rows; ++t) K += fmix64((row0[t] + (uint64_t)t * 0x9E3779B97F4A7C15ull) ^ salt_m);
+  return K;
+}
+
 // Band key of one band: sum over its r rows of fmix64((v | t << 32) ^ salt).
 LB_FN uint64_t band_key(const uint32_t *row0, uint32_t rows, uint64_t salt_m) {
   uint64_t K = 0;

@@ -60,6 +60,9 @@ int check_ready(lshbloom *h);
 // ordering events, no counters); the algorithm follows the handle's mode.
 // Returns LSHBLOOM_OK or an error code (message set, handle poisoned on a
 // HIP error).
-int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n, uint8_t *d_flags, hipStream_t s);
+// With d_keys (band keys [n][bands]) the keys are taken as given and d_sigs
+// is not read.
+int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n, uint8_t *d_flags, hipStream_t s,
+               const uint64_t *d_keys = nullptr);
 
 }  // namespace lbh

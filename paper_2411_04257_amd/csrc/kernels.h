@@ -19,6 +19,9 @@ struct MinhashLaunch {
   int64_t n_docs;
   const PermCoef *coef;
   uint32_t *sigs;
+  // wide-value variant: when set, signatures are the whole 61-bit
+  // permutation values written here (and sigs is unused)
+  uint64_t *sigs64;
   uint32_t num_perm;
   uint32_t w;
   int waves;  // total waves of the persistent grid (multiple of 4)
@@ -31,6 +34,8 @@ struct MinhashLaunch {
 
 struct BloomLaunch {
   const uint32_t *sigs;  // [n][num_perm]
+  const uint64_t *keys_in;   // [n][bands] band keys given by the caller (instead of sigs), or null
+  const uint64_t *sigs64;    // [n][num_perm] wide signatures (k_band_keys61 only)
   int64_t n;
   uint32_t num_perm, bands, rows, k;
   uint64_t m_bits, words_per_band;
@@ -49,6 +54,8 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_fill_u64(uint64_t *p, uint64_t n, uint64_t v, hipStream_t s);
 hipError_t launch_minhash(const MinhashLaunch &a, hipStream_t s);
 hipError_t launch_band_keys(const BloomLaunch &a, hipStream_t s);
+// Band keys of wide signatures (a.sigs64) into a.keys [n][bands].
+hipError_t launch_band_keys61(const BloomLaunch &a, hipStream_t s);
 // One in-order chunk: clear table, probe, resolve + insert, flags.
 hipError_t launch_query_insert_chunk(const BloomLaunch &a, uint64_t table_slots, hipStream_t s);
 hipError_t launch_query(const BloomLaunch &a, hipStream_t s);

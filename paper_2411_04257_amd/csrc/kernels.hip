@@ -22,6 +22,8 @@
 //  k_qi_flags  : OR over bands (Section 4.2).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device_math.h"
 #include "kernels.h"
 
@@ -65,8 +67,12 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
 // PPL = 2; 96 gives 5).
 constexpr int minhash_min_waves(int ppl) { return ppl <= 2 ? 5 : (ppl <= 4 ? 4 : 3); }
 
-template <int PPL, int WFIX>
+// WIDE: the signature values are the whole 61-bit permutation values
+// (uint64 rows in A.sigs64) instead of their low 32 bits.
+template <int PPL, int WFIX, bool WIDE>
 __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(MinhashLaunch A) {
+  using V = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
+  constexpr V kEmpty = ~(V)0;
   const int lane = threadIdx.x & 63;
   const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
   const int64_t n_docs = A.n_docs;
@@ -80,7 +86,8 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
 
   const uint32_t P = A.num_perm;
   const int64_t w = WFIX ? WFIX : (int64_t)A.w;
-  uint32_t al[PPL], ah[PPL], bl[PPL], bh[PPL], mn[PPL];
+  uint32_t al[PPL], ah[PPL], bl[PPL], bh[PPL];
+  V mn[PPL];
 #pragma unroll
   for (int p = 0; p < PPL; ++p) {
     const uint32_t i = (uint32_t)p * 64u + (uint32_t)lane;
@@ -90,7 +97,7 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
     ah[p] = c.a_hi;
     bl[p] = c.b_lo;
     bh[p] = c.b_hi;
-    mn[p] = 0xFFFFFFFFu;
+    mn[p] = kEmpty;
   }
 
   // Document containing the first position of the current tile.
@@ -101,17 +108,32 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
     const int64_t s0 = A.offsets[d], e0 = A.offsets[d + 1];
     const int64_t last = (e0 - s0 >= w) ? e0 - w : s0;
     const bool inside = s0 >= r0 && last < r1;
-    uint32_t *row = A.sigs + (A.row_ids ? A.row_ids[d] : d) * (int64_t)P;
+    if constexpr (WIDE) {
+      uint64_t *row = A.sigs64 + (A.row_ids ? A.row_ids[d] : d) * (int64_t)P;
 #pragma unroll
-    for (int p = 0; p < PPL; ++p) {
-      const uint32_t i = (uint32_t)p * 64u + (uint32_t)lane;
-      if (i < P) {
-        if (inside)
-          row[i] = mn[p];
-        else
-          atomicMin(&row[i], mn[p]);
+      for (int p = 0; p < PPL; ++p) {
+        const uint32_t i = (uint32_t)p * 64u + (uint32_t)lane;
+        if (i < P) {
+          if (inside)
+            row[i] = mn[p];
+          else
+            atomicMin((unsigned long long *)&row[i], (unsigned long long)mn[p]);
+        }
+        mn[p] = kEmpty;
       }
-      mn[p] = 0xFFFFFFFFu;
+    } else {
+      uint32_t *row = A.sigs + (A.row_ids ? A.row_ids[d] : d) * (int64_t)P;
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        const uint32_t i = (uint32_t)p * 64u + (uint32_t)lane;
+        if (i < P) {
+          if (inside)
+            row[i] = mn[p];
+          else
+            atomicMin(&row[i], mn[p]);
+        }
+        mn[p] = kEmpty;
+      }
     }
   };
 
@@ -180,6 +202,18 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
         sm &= sm - 1;
         const uint32_t x0 = __builtin_amdgcn_readlane(x, s0);
         const uint32_t x1 = __builtin_amdgcn_readlane(x, s1);
+        if constexpr (WIDE) {
+          // the canonical value: R < 2p, one conditional subtraction
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) {
+            uint64_t c0 = perm_r(x0, al[p], ah[p], bl[p], bh[p]);
+            uint64_t c1 = perm_r(x1, al[p], ah[p], bl[p], bh[p]);
+            c0 = c0 >= kP61 ? c0 - kP61 : c0;
+            c1 = c1 >= kP61 ? c1 - kP61 : c1;
+            mn[p] = min(mn[p], min(c0, c1));
+          }
+          continue;
+        }
         // Common path: the Mersenne-folded R without its canonical
         // correction, plus one compare per evaluation whose lane mask is
         // OR-ed on the scalar unit.  R >= p (probability ~2^-29 per
@@ -203,7 +237,7 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
           }
         }
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], min(v0[p], v1[p]));
+        for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], (V)min(v0[p], v1[p]));
       }
     }
     dcur = dnext;
@@ -235,6 +269,14 @@ __device__ __forceinline__ uint64_t table_slot(uint64_t key, uint64_t mask) {
   return fmix64(key * 0x9E3779B97F4A7C15ull + 0x632BE59BD9B4E019ull) & mask;
 }
 
+__global__ __launch_bounds__(kBlock) void k_band_keys61(BloomLaunch A) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= A.n * (int64_t)A.bands) return;
+  const int64_t i = t / A.bands;
+  const uint32_t j = (uint32_t)(t - i * A.bands);
+  A.keys[t] = band_key61(A.sigs64 + i * (int64_t)A.num_perm + (int64_t)j * A.rows, A.rows, A.salt_m);
+}
+
 __global__ __launch_bounds__(kBlock) void k_band_keys(BloomLaunch A) {
   const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (t >= A.n * (int64_t)A.bands) return;
@@ -250,7 +292,8 @@ __global__ __launch_bounds__(kBlock) void k_qi_probe(BloomLaunch A) {
   if (t >= A.n * (int64_t)A.bands) return;
   const int64_t i = t / A.bands;
   const uint32_t j = (uint32_t)(t - i * A.bands);
-  const uint64_t K = band_key(A.sigs + i * (int64_t)A.num_perm + (int64_t)j * A.rows, A.rows, A.salt_m);
+  const uint64_t K = A.keys_in ? A.keys_in[t]
+                              : band_key(A.sigs + i * (int64_t)A.num_perm + (int64_t)j * A.rows, A.rows, A.salt_m);
   A.keys[t] = K;
   const uint64_t h1 = fmix64(K ^ A.salt1);
   const uint64_t h2 = fmix64(K ^ A.salt2) | 1ull;
@@ -403,12 +446,19 @@ hipError_t launch_minhash(const MinhashLaunch &a, hipStream_t s) {
   const unsigned blocks = (unsigned)(a.waves / (kBlock / 64));
   const int ppl = (int)((a.num_perm + 63) / 64);
   const bool w5 = a.w == 5;
-#define LB_MH(PPL_)                                                                        \
-  do {                                                                                     \
-    if (w5)                                                                                \
-      hipLaunchKernelGGL((k_minhash<PPL_, 5>), dim3(blocks), dim3(kBlock), 0, s, a);       \
-    else                                                                                   \
-      hipLaunchKernelGGL((k_minhash<PPL_, 0>), dim3(blocks), dim3(kBlock), 0, s, a);       \
+  const bool wide = a.sigs64 != nullptr;
+#define LB_MH(PPL_)                                                                              \
+  do {                                                                                           \
+    if (wide) {                                                                                  \
+      if (w5)                                                                                    \
+        hipLaunchKernelGGL((k_minhash<PPL_, 5, true>), dim3(blocks), dim3(kBlock), 0, s, a);     \
+      else                                                                                       \
+        hipLaunchKernelGGL((k_minhash<PPL_, 0, true>), dim3(blocks), dim3(kBlock), 0, s, a);     \
+    } else if (w5) {                                                                             \
+      hipLaunchKernelGGL((k_minhash<PPL_, 5, false>), dim3(blocks), dim3(kBlock), 0, s, a);      \
+    } else {                                                                                     \
+      hipLaunchKernelGGL((k_minhash<PPL_, 0, false>), dim3(blocks), dim3(kBlock), 0, s, a);      \
+    }                                                                                            \
   } while (0)
   if (ppl <= 1)
     LB_MH(1);
@@ -426,6 +476,13 @@ hipError_t launch_band_keys(const BloomLaunch &a, hipStream_t s) {
   const uint64_t n = (uint64_t)a.n * a.bands;
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_band_keys, dim3(grid_for(n)), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_band_keys61(const BloomLaunch &a, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.n * a.bands;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_band_keys61, dim3(grid_for(n)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }
 

@@ -169,7 +169,8 @@ lb::BloomLaunch bloom_args(lshbloom *h, const uint32_t *sigs, int64_t n) {
 
 namespace lbh {
 
-int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags, hipStream_t s) {
+int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags, hipStream_t s,
+               const uint64_t *d_keys) {
   hipError_t e;
   const uint64_t pd = (uint64_t)h->prm.bands * h->k;
   const bool binned = h->bin_chunk && (h->qi_mode == 2 || (h->qi_mode == 0 && n_docs >= kBinnedMinDocs));
@@ -178,7 +179,8 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
       const int64_t cn = std::min<int64_t>((int64_t)h->bin_chunk, n_docs - c0);
       const lb::BinnedGeometry G = lb::binned_geometry((uint64_t)cn, h->prm.bands, h->k, h->m_bits);
       lb::BinnedLaunch a{};
-      a.sigs = d_sigs + c0 * (int64_t)h->prm.num_perm;
+      a.sigs = d_keys ? nullptr : d_sigs + c0 * (int64_t)h->prm.num_perm;
+      a.keys_in = d_keys ? d_keys + c0 * (int64_t)h->prm.bands : nullptr;
       a.n = cn;
       a.num_perm = h->prm.num_perm;
       a.bands = h->prm.bands;
@@ -216,7 +218,8 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
   }
   for (int64_t c0 = 0; c0 < n_docs; c0 += (int64_t)h->chunk_docs) {
     const int64_t cn = std::min<int64_t>((int64_t)h->chunk_docs, n_docs - c0);
-    lb::BloomLaunch a = bloom_args(h, d_sigs + c0 * (int64_t)h->prm.num_perm, cn);
+    lb::BloomLaunch a = bloom_args(h, d_keys ? nullptr : d_sigs + c0 * (int64_t)h->prm.num_perm, cn);
+    a.keys_in = d_keys ? d_keys + c0 * (int64_t)h->prm.bands : nullptr;
     a.flags = d_flags + c0;
     const uint64_t slots = std::min<uint64_t>(h->table_slots_max, next_pow2(std::max<uint64_t>(1024, 2 * cn * pd)));
     a.table_mask = slots - 1;
@@ -602,6 +605,72 @@ int lshbloom_band_keys(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, ui
   a.keys = d_keys;
   hipError_t e = lb::launch_band_keys(a, (hipStream_t)stream);
   if (e != hipSuccess) return fail_hip(nullptr, e, "band_keys: launch");
+  return LSHBLOOM_OK;
+}
+
+int lshbloom_minhash61(lshbloom_t *h, const int64_t *d_offsets, const uint32_t *d_tokens, int64_t n_docs,
+                       uint64_t *d_sigs, lshbloom_stream_t stream) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (n_docs < 0 || (n_docs > 0 && (!d_offsets || !d_sigs || !d_tokens))) {
+    set_err("minhash61: need n_docs >= 0 and non-null offsets, tokens and sigs");
+    return LSHBLOOM_EINVAL;
+  }
+  if (n_docs == 0) return LSHBLOOM_OK;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = lb::launch_fill_u64(d_sigs, (uint64_t)n_docs * h->prm.num_perm, ~0ull, s);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "minhash61: fill");
+  lb::MinhashLaunch a{};
+  a.offsets = d_offsets;
+  a.tokens = d_tokens;
+  a.n_docs = n_docs;
+  a.coef = h->d_coef;
+  a.sigs64 = d_sigs;
+  a.num_perm = h->prm.num_perm;
+  a.w = h->prm.shingle_width;
+  a.waves = h->minhash_waves ? h->minhash_waves : lb::minhash_waves_for_docs(h->cus, (uint64_t)n_docs);
+  e = lb::launch_minhash(a, s);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "minhash61: launch");
+  return LSHBLOOM_OK;
+}
+
+int lshbloom_band_keys61(lshbloom_t *h, const uint64_t *d_sigs, int64_t n_docs, uint64_t *d_keys,
+                         lshbloom_stream_t stream) {
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (n_docs < 0 || (n_docs > 0 && (!d_sigs || !d_keys))) {
+    set_err("band_keys61: need n_docs >= 0 and non-null sigs and keys");
+    return LSHBLOOM_EINVAL;
+  }
+  if (n_docs == 0) return LSHBLOOM_OK;
+  lb::BloomLaunch a = bloom_args(h, nullptr, n_docs);
+  a.sigs64 = d_sigs;
+  a.keys = d_keys;
+  hipError_t e = lb::launch_band_keys61(a, (hipStream_t)stream);
+  if (e != hipSuccess) return fail_hip(nullptr, e, "band_keys61: launch");
+  return LSHBLOOM_OK;
+}
+
+int lshbloom_query_insert_keys(lshbloom_t *h, const uint64_t *d_keys, int64_t n_docs, uint8_t *d_flags,
+                               lshbloom_stream_t stream) {
+  if (!h) return check_ready(h);
+  std::lock_guard<std::mutex> lk(h->mu);
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (n_docs < 0 || (n_docs > 0 && (!d_keys || !d_flags))) {
+    set_err("query_insert_keys: need n_docs >= 0 and non-null keys and flags");
+    return LSHBLOOM_EINVAL;
+  }
+  if (n_docs == 0) return LSHBLOOM_OK;
+  if (forced_fault(h)) return LSHBLOOM_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = begin_ordered(h, s);
+  if (e != hipSuccess) return fail_hip(h, e, "query_insert_keys: stream wait");
+  rc = lbh::qi_enqueue(h, nullptr, n_docs, d_flags, s, d_keys);
+  if (rc) return rc;
+  e = end_ordered(h, s);
+  if (e != hipSuccess) return fail_hip(h, e, "query_insert_keys: event");
+  h->docs_inserted += (uint64_t)n_docs;
   return LSHBLOOM_OK;
 }
 

@@ -31,6 +31,7 @@ struct BinnedGeometry {
 
 struct BinnedLaunch {
   const uint32_t *sigs;  // [n][num_perm]
+  const uint64_t *keys_in;  // [n][bands] band keys given by the caller (instead of sigs), or null
   int64_t n;
   uint32_t num_perm, bands, rows, k;
   uint64_t m_bits, words_per_band;

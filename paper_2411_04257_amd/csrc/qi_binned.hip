@@ -140,6 +140,15 @@ __global__ __launch_bounds__(256) void k_bq_keys(BinnedLaunch A) {
   }
 }
 
+// Band keys given by the caller, [n][bands] -> band-major.
+__global__ __launch_bounds__(256) void k_bq_keys_in(BinnedLaunch A) {
+  const int64_t t = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= A.n * (int64_t)A.bands) return;
+  const int64_t d = t / A.bands;
+  const uint32_t j = (uint32_t)(t - d * A.bands);
+  A.keys[(int64_t)j * A.n + d] = A.keys_in[t];
+}
+
 // ---------------------------------------------------------------- pass 1 ----
 // Block (tile of 1024 documents, band j).  k_bq_count1: per-bucket record
 // counts of the block.  k_bq_scatter1 (1024 threads, one block per compute
@@ -860,7 +869,10 @@ hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s) {
   hipError_t e;
   const uint32_t td = keys_tile_docs(a.bands * a.rows);
   const size_t ldsk = (size_t)td * (a.bands * a.rows + 1) * 4;
-  hipLaunchKernelGGL(k_bq_keys, dim3(grid1((uint64_t)a.n, td)), dim3(kThreads), ldsk, s, a);
+  if (a.keys_in)
+    hipLaunchKernelGGL(k_bq_keys_in, dim3(grid1((uint64_t)a.n * a.bands, kThreads)), dim3(kThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_bq_keys, dim3(grid1((uint64_t)a.n, td)), dim3(kThreads), ldsk, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bq_count1, dim3(G.n_tiles, a.bands), dim3(kThreads), (size_t)G.buckets_per_band * 4, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;

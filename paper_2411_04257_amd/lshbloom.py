@@ -101,6 +101,7 @@ EXPORTS = [
     "lshbloom_pipeline_create", "lshbloom_pipeline_submit", "lshbloom_pipeline_wait", "lshbloom_pipeline_poll",
     "lshbloom_pipeline_info", "lshbloom_pipeline_destroy",
     "lshbloom_exact_create", "lshbloom_exact_destroy", "lshbloom_exact_query_insert", "lshbloom_exact_stats",
+    "lshbloom_query_insert_keys", "lshbloom_minhash61", "lshbloom_band_keys61",
 ]
 
 _lib = None
@@ -148,6 +149,12 @@ def load(path: str = LIB_PATH):
     L.lshbloom_pipeline_info.restype = ctypes.c_int
     L.lshbloom_pipeline_destroy.argtypes = [vp]
     L.lshbloom_pipeline_destroy.restype = None
+    L.lshbloom_query_insert_keys.argtypes = [vp, vp, i64, vp, vp]
+    L.lshbloom_query_insert_keys.restype = ctypes.c_int
+    L.lshbloom_minhash61.argtypes = [vp, vp, vp, i64, vp, vp]
+    L.lshbloom_minhash61.restype = ctypes.c_int
+    L.lshbloom_band_keys61.argtypes = [vp, vp, i64, vp, vp]
+    L.lshbloom_band_keys61.restype = ctypes.c_int
     L.lshbloom_exact_create.argtypes = [u32, u32, u32, u64, u32]
     L.lshbloom_exact_create.restype = vp
     L.lshbloom_exact_destroy.argtypes = [vp]
@@ -280,6 +287,44 @@ class LSHBloom:
         if n:
             _check(load().lshbloom_band_keys(self._h, _dev_ptr(sigs, _U32, "sigs"), n,
                                              _dev_ptr(out, (torch.int64,), "out"), _stream()))
+        return out
+
+    def query_insert_keys(self, keys: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Query-insert from band keys int64 [n, bands] (uint64 bit patterns)."""
+        if keys.dim() != 2 or keys.shape[1] != self.bands:
+            raise ValueError("keys must have shape [n_docs, bands]")
+        n = keys.shape[0]
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=keys.device)
+        if n:
+            _check(load().lshbloom_query_insert_keys(self._h, _dev_ptr(keys, (torch.int64, torch.uint64), "keys"), n,
+                                                     _dev_ptr(out, (torch.uint8,), "out"), _stream()))
+        return out
+
+    # -- wide-value variant (61-bit signature values) --------------------------
+    def minhash61(self, offsets: torch.Tensor, tokens: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        """Signatures int64 [n_docs, num_perm] of whole 61-bit permutation values."""
+        n = offsets.numel() - 1
+        if out is None:
+            out = torch.empty((max(n, 0), self.num_perm), dtype=torch.int64, device=offsets.device)
+        if n <= 0:
+            return out
+        if out.shape != (n, self.num_perm):
+            raise ValueError("out must have shape [n_docs, num_perm]")
+        _check(load().lshbloom_minhash61(self._h, _dev_ptr(offsets, (torch.int64,), "offsets"),
+                                         _dev_ptr(tokens, _U32, "tokens") if tokens.numel() else ctypes.c_void_p(
+                                             offsets.data_ptr()),
+                                         n, _dev_ptr(out, (torch.int64, torch.uint64), "out"), _stream()))
+        return out
+
+    def band_keys61(self, sigs: torch.Tensor) -> torch.Tensor:
+        if sigs.dim() != 2 or sigs.shape[1] != self.num_perm:
+            raise ValueError("sigs must have shape [n_docs, num_perm]")
+        n = sigs.shape[0]
+        out = torch.empty((n, self.bands), dtype=torch.int64, device=sigs.device)
+        if n:
+            _check(load().lshbloom_band_keys61(self._h, _dev_ptr(sigs, (torch.int64, torch.uint64), "sigs"), n,
+                                               _dev_ptr(out, (torch.int64,), "out"), _stream()))
         return out
 
     # -- filters -------------------------------------------------------------

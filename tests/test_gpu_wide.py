@@ -1,0 +1,128 @@
+"""GPU parity of the wide-value variant (61-bit signature values, their band
+keys) and of query-insert from band keys, through the C ABI, against the CPU
+oracle: bit-exact signatures, keys, flags and filter words.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_04257_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+QI_MODES = pytest.mark.parametrize("qi_mode", [1, 2], ids=["direct", "binned"])
+
+
+def _csr(docs):
+    lens = [len(d) for d in docs]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    tok = np.concatenate([np.asarray(d, dtype=np.uint32) for d in docs]) if sum(lens) else np.zeros(0, np.uint32)
+    return off, tok
+
+
+def _to_gpu(offsets, tokens):
+    off = torch.as_tensor(np.ascontiguousarray(offsets, dtype=np.int64)).cuda()
+    tok = torch.as_tensor(np.ascontiguousarray(tokens, dtype=np.uint32).view(np.int32)).cuda()
+    return off, tok
+
+
+def _u64(t: torch.Tensor) -> np.ndarray:
+    return t.cpu().numpy().view(np.uint64)
+
+
+def test_minhash61_edge_cases(gpu):
+    rng = np.random.default_rng(31)
+    docs = [[], [7], [1, 2], [1, 2, 3, 4], [1, 2, 3, 4, 5], [5, 4, 3, 2, 1, 0]]
+    docs += [[] for _ in range(100)]
+    docs += [rng.integers(0, 50000, int(L)).tolist() for L in [1, 3, 4, 5, 6, 63, 64, 65, 127, 128, 129]]
+    docs += [[9] * 50]
+    docs += [rng.integers(0, 2**32, 300_000, dtype=np.uint64).astype(np.uint32)]  # spans many wave ranges
+    docs += [[], []]
+    off, tok = _csr(docs)
+    print("minhash61 edge cases", flush=True)
+    g = gpu.LSHBloom(128, 16, 8, 2000, 1e-5, 42)
+    o = oracle.OracleIndex(128, 16, 8, 2000, 1e-5, 42)
+    want = o.minhash61(off, tok)
+    doff, dtok = _to_gpu(off, tok)
+    got = _u64(g.minhash61(doff, dtok))
+    np.testing.assert_array_equal(got, want)
+    assert (want[0] == np.uint64(2**64 - 1)).all()
+    assert (want[1] < np.uint64((1 << 61) - 1)).all()
+    g.close()
+
+
+@pytest.mark.parametrize("num_perm,w", [(128, 5), (256, 5), (48, 5), (512, 13), (64, 1)])
+def test_minhash61_widths_and_perm_counts(gpu, num_perm, w):
+    wl = synth.WORKLOADS["c3"]
+    corpus = synth.make_corpus(wl, n_docs=3000, seed=12)
+    off = corpus.offsets.numpy()
+    tok = corpus.tokens.numpy().view(np.uint32)
+    bands = min(16, num_perm // 4)
+    print(f"minhash61 P={num_perm} w={w}", flush=True)
+    g = gpu.LSHBloom(num_perm, bands, 4, 3000, 1e-5, 7, shingle_width=w)
+    o = oracle.OracleIndex(num_perm, bands, 4, 3000, 1e-5, 7, w)
+    doff, dtok = _to_gpu(off, tok)
+    sigs = g.minhash61(doff, dtok)
+    want = o.minhash61(off, tok)
+    np.testing.assert_array_equal(_u64(sigs), want)
+    np.testing.assert_array_equal(_u64(g.band_keys61(sigs)), o.band_keys61(want))
+    g.close()
+
+
+@QI_MODES
+def test_wide_pipeline_end_to_end(gpu, qi_mode):
+    """c1's corpus through the wide chain: MinHash of 61-bit values, their
+    band keys, query-insert from keys; flags and filters bit-exact."""
+    wl = synth.WORKLOADS["c1"]
+    corpus = synth.make_corpus(wl)
+    off = corpus.offsets.numpy()
+    tok = corpus.tokens.numpy().view(np.uint32)
+    print(f"wide pipeline qi_mode={qi_mode}", flush=True)
+    g = gpu.LSHBloom(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed, qi_mode=qi_mode)
+    o = oracle.OracleIndex(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
+    doff, dtok = _to_gpu(off, tok)
+    keys = g.band_keys61(g.minhash61(doff, dtok))
+    want_keys = o.band_keys61(o.minhash61(off, tok))
+    np.testing.assert_array_equal(_u64(keys), want_keys)
+    flags = np.concatenate([g.query_insert_keys(keys[a:b]).cpu().numpy() for a, b in [(0, 700), (700, 2000)]])
+    want = o.query_insert_keys(want_keys)
+    np.testing.assert_array_equal(flags, want)
+    np.testing.assert_array_equal(g.read_filters().cpu().numpy().view(np.uint64), o.filters())
+    assert want.sum() > 50
+    g.close()
+
+
+@QI_MODES
+@pytest.mark.parametrize("chunk_docs", [0, 777])
+def test_query_insert_keys_equals_query_insert(gpu, qi_mode, chunk_docs):
+    """Query-insert from the band keys of signatures gives the flags and the
+    filters of query-insert from the signatures (in-batch repeats, uneven
+    calls, chunks)."""
+    n = 6000
+    s = synth.signature_batch(0, n, 128, 16, 8, n, 0.3, 0.5, 17).numpy().view(np.uint32)
+    d = torch.from_numpy(s.view(np.int32).copy()).cuda()
+    print(f"keys vs sigs qi_mode={qi_mode} chunk={chunk_docs}", flush=True)
+    g1 = gpu.LSHBloom(128, 16, 8, n, 1e-4, 42, qi_mode=qi_mode, chunk_docs=chunk_docs)
+    g2 = gpu.LSHBloom(128, 16, 8, n, 1e-4, 42, qi_mode=qi_mode, chunk_docs=chunk_docs)
+    f1 = g1.query_insert(d).cpu().numpy()
+    keys = g2.band_keys(d)
+    f2 = np.concatenate([g2.query_insert_keys(keys[a:b]).cpu().numpy() for a, b in [(0, 1), (1, 4500), (4500, n)]])
+    np.testing.assert_array_equal(f1, f2)
+    assert f1.sum() > 1000
+    np.testing.assert_array_equal(g1.read_filters().cpu().numpy(), g2.read_filters().cpu().numpy())
+    o = oracle.OracleIndex(128, 16, 8, n, 1e-4, 42)
+    np.testing.assert_array_equal(o.query_insert_keys(keys.cpu().numpy().view(np.uint64)), f1)
+    g1.close()
+    g2.close()
+
+
+def test_keys_path_rejects_bad_arguments(gpu):
+    g = gpu.LSHBloom(128, 16, 8, 1000, 1e-4, 42)
+    with pytest.raises(ValueError):
+        g.query_insert_keys(torch.zeros((10, 15), dtype=torch.int64, device="cuda"))
+    assert gpu.load().lshbloom_query_insert_keys(g._h, None, 5, None, None) == gpu.EINVAL
+    assert gpu.load().lshbloom_minhash61(g._h, None, None, 5, None, None) == gpu.EINVAL
+    assert g.info()["docs_inserted"] == 0
+    g.close()
