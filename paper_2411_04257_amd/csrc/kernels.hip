@@ -203,15 +203,25 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
         const uint32_t x0 = __builtin_amdgcn_readlane(x, s0);
         const uint32_t x1 = __builtin_amdgcn_readlane(x, s1);
         if constexpr (WIDE) {
-          // the canonical value: R < 2p, one conditional subtraction
+          // the canonical value: R < 2p needs one conditional subtraction,
+          // taken (as below for 32-bit values) only when some lane has R >= p
+          uint64_t c0[PPL], c1[PPL];
+          uint64_t ge = 0;
 #pragma unroll
           for (int p = 0; p < PPL; ++p) {
-            uint64_t c0 = perm_r(x0, al[p], ah[p], bl[p], bh[p]);
-            uint64_t c1 = perm_r(x1, al[p], ah[p], bl[p], bh[p]);
-            c0 = c0 >= kP61 ? c0 - kP61 : c0;
-            c1 = c1 >= kP61 ? c1 - kP61 : c1;
-            mn[p] = min(mn[p], min(c0, c1));
+            c0[p] = perm_r(x0, al[p], ah[p], bl[p], bh[p]);
+            c1[p] = perm_r(x1, al[p], ah[p], bl[p], bh[p]);
+            ge |= __ballot(c0[p] >= kP61) | __ballot(c1[p] >= kP61);
           }
+          if (ge) {
+#pragma unroll
+            for (int p = 0; p < PPL; ++p) {
+              c0[p] = c0[p] >= kP61 ? c0[p] - kP61 : c0[p];
+              c1[p] = c1[p] >= kP61 ? c1[p] - kP61 : c1[p];
+            }
+          }
+#pragma unroll
+          for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], min(c0[p], c1[p]));
           continue;
         }
         // Common path: the Mersenne-folded R without its canonical

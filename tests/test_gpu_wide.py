@@ -126,3 +126,44 @@ def test_keys_path_rejects_bad_arguments(gpu):
     assert gpu.load().lshbloom_minhash61(g._h, None, None, 5, None, None) == gpu.EINVAL
     assert g.info()["docs_inserted"] == 0
     g.close()
+
+
+def test_minhash61_rare_canonical_correction(gpu):
+    """The wide kernel, like the 32-bit one, subtracts p only when some
+    lane's folded value R is >= 2^61 - 1 (about 2^-29 per evaluation).
+    Single-token shingles and index seeds that reach that path are found by
+    evaluating R for 2^20 tokens, then checked bit for bit."""
+    import hashlib
+
+    P61 = (1 << 61) - 1
+    n_tok = 1 << 20
+    toks = np.arange(n_tok, dtype=np.uint32)
+    xs = np.frombuffer(b"".join(hashlib.sha1(int(t).to_bytes(4, "little")).digest()[:4] for t in toks),
+                       dtype="<u4").astype(np.int64)
+    xg = torch.as_tensor(xs, device="cuda")
+    M32 = 0xFFFFFFFF
+    found = []
+    for seed in range(1, 65):
+        a, b, _ = oracle.OracleIndex(128, 16, 8, 1000, 1e-3, seed, 1).coeffs()
+        for i in range(128):
+            al, ah = int(a[i]) & M32, int(a[i]) >> 32
+            bl, bh = int(b[i]) & M32, int(b[i]) >> 32
+            Pv = xg * al + bl  # wraps mod 2^64; only its two 32-bit halves are used
+            P_lo, P_hi = Pv & M32, (Pv >> 32) & M32
+            Q = xg * ah + bh + P_hi
+            R = (((Q & 0x1FFFFFFF) << 32) | P_lo) + (Q >> 29)
+            hit = torch.nonzero(R >= P61).flatten()
+            if hit.numel():
+                found += [(seed, int(t)) for t in hit.cpu().numpy()]
+        if len(found) >= 3:
+            break
+    assert found
+    rng = np.random.default_rng(22)
+    for seed, tok in found[:4]:
+        docs = [[tok], rng.integers(0, n_tok, 50).tolist() + [tok] + rng.integers(0, n_tok, 50).tolist(), [tok] * 3]
+        off, tk = _csr(docs)
+        g = gpu.LSHBloom(128, 16, 8, 1000, 1e-3, seed, shingle_width=1)
+        o = oracle.OracleIndex(128, 16, 8, 1000, 1e-3, seed, 1)
+        doff, dtok = _to_gpu(off, tk)
+        np.testing.assert_array_equal(_u64(g.minhash61(doff, dtok)), o.minhash61(off, tk))
+        g.close()
