@@ -451,7 +451,7 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
     LB_ALLOC(h->d_rec1, bin_chunk * probes_per_doc * 16);
     LB_ALLOC(h->d_rec2, bin_chunk * probes_per_doc * 8);
     LB_ALLOC(h->d_bkeys, bin_chunk * prm.bands * 8);
-    LB_ALLOC(h->d_res0, bin_chunk * prm.bands);
+    LB_ALLOC(h->d_res0, (bin_chunk * prm.bands + 15) & ~15ull);  // zeroed as 32-bit words
   }
   LB_ALLOC(h->d_coef, prm.num_perm * sizeof(lb::PermCoef));
   LB_ALLOC(h->d_status, 256);

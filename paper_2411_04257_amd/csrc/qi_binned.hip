@@ -37,6 +37,8 @@
 // tables hold take a slower path with their table in global memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device_math.h"
 #include "qi_binned.h"
 
@@ -138,6 +140,13 @@ __global__ __launch_bounds__(256) void k_bq_keys(BinnedLaunch A) {
     const uint32_t j = p / nd, d = p - j * nd;
     A.keys[(int64_t)j * A.n + d0 + d] = band_key(&srow[d * stride + j * A.rows], A.rows, A.salt_m);
   }
+}
+
+// Zero the probe-0 answers of a chunk (their bytes as 32-bit words).
+__global__ __launch_bounds__(256) void k_bq_zero_res0(BinnedLaunch A, uint64_t words) {
+  uint32_t *w = reinterpret_cast<uint32_t *>(A.res0);
+  for (uint64_t q = (uint64_t)blockIdx.x * kThreads + threadIdx.x; q < words; q += (uint64_t)gridDim.x * kThreads)
+    w[q] = 0;
 }
 
 // Band keys given by the caller, [n][bands] -> band-major.
@@ -456,7 +465,7 @@ __device__ void bin_global(const BinnedLaunch &A, uint32_t j, uint64_t bin, uint
         }
         h = (h + 1 == cap) ? 0 : h + 1;
       }
-      A.res0[(int64_t)j * A.n + i] = (v == kInit || v < i) ? 1 : 0;
+      if (v == kInit || v < i) A.res0[(int64_t)j * A.n + i] = 1;  // res0 starts zeroed
     }
   }
   if (lane == 0) A.dir[bin] = ((uint64_t)r0 << 32) | cap;
@@ -650,7 +659,8 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
       if (u >= nu) continue;
       const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
       const uint32_t v = tmin[slot[u]];
-      if (rec[u] & kProbe0) A.res0[(int64_t)j * A.n + i] = v <= i ? 1 : 0;
+      // res0 starts zeroed: only the set-before answers are written
+      if ((rec[u] & kProbe0) && v <= i) A.res0[(int64_t)j * A.n + i] = 1;
       const bool clr = !(init >> u & 1u);
       if (clr && v != i + 1) atomicOr(&tkey[slot[u]], kMulti);  // rare: skipped by most rows
       const uint32_t lb = key1[u] - 1, lw = lb >> 6;
@@ -732,10 +742,10 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     const uint32_t pcap = min(2 * mine, room);
     wave_sync();
     if (DIRECT) {
+      // the table's first pcap entries, two per 16-byte store
       uint4 *w4 = reinterpret_cast<uint4 *>(wv);
       const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-#pragma unroll
-      for (uint32_t t = 0; t < kWRegion / 128; ++t) w4[t * 64 + lane] = z;
+      for (uint32_t q = lane; 2 * q < pcap; q += 64) w4[q] = z;
     } else {
 #pragma unroll
       for (uint32_t t = 0; t < kWTab / 64; ++t) {
@@ -869,6 +879,11 @@ hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s) {
   hipError_t e;
   const uint32_t td = keys_tile_docs(a.bands * a.rows);
   const size_t ldsk = (size_t)td * (a.bands * a.rows + 1) * 4;
+  {
+    const uint64_t words = ((uint64_t)a.n * a.bands + 3) / 4;  // the allocation is padded to 16 bytes
+    const uint64_t g = std::min<uint64_t>((words + kThreads - 1) / kThreads, 4096);
+    hipLaunchKernelGGL(k_bq_zero_res0, dim3((unsigned)std::max<uint64_t>(g, 1)), dim3(kThreads), 0, s, a, words);
+  }
   if (a.keys_in)
     hipLaunchKernelGGL(k_bq_keys_in, dim3(grid1((uint64_t)a.n * a.bands, kThreads)), dim3(kThreads), 0, s, a);
   else
