@@ -735,9 +735,11 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
         }
       }
     }
-    uint32_t mine = __popc(ib);
+    // entries of the whole wave: one ballot per record row (scalar work, no
+    // cross-lane shuffles)
+    uint32_t mine = 0;
 #pragma unroll
-    for (uint32_t off = 32; off > 0; off >>= 1) mine += __shfl_xor(mine, off, 64);
+    for (uint32_t u = 0; u < kWPer; ++u) mine += (uint32_t)__popcll(__ballot((ib >> u) & 1u));
     const uint32_t room = DIRECT ? kWRegion : kWTab;
     const uint32_t pcap = min(2 * mine, room);
     wave_sync();
