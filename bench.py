@@ -72,7 +72,7 @@ def parse():
                     help="instead of a workload: measure the memory system's ceilings with torch's own kernels "
                          "(streaming copy, random 8-byte gather and scatter over a GB-sized buffer) and exit")
     a = ap.parse_args()
-    default_steps = {"c2": (13, 2), "c3": (4, 1), "c4": (20, 2), "c5": (0, 0)}[a.workload]
+    default_steps = {"c2": (13, 2), "c3": (9, 1), "c4": (20, 2), "c5": (0, 0)}[a.workload]
     if a.steps is None:
         a.steps = default_steps[0]
     if a.warmup is None:
