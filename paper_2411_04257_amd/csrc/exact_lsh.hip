@@ -166,7 +166,9 @@ __global__ __launch_bounds__(kT) void k_ex_flags(ExLaunch A) {
   uint8_t hit = 0;
   for (uint32_t j = 0; j < A.bands; ++j) {
     const uint32_t s = A.slot[i * A.bands + j] & ~kOwner;
-    hit |= A.first[(uint64_t)j * A.slots + s] < doc ? 1 : 0;
+    // every item has a slot (the tables are at most half full); the bound
+    // keeps a broken invariant from reading outside them
+    if (s < A.slots) hit |= A.first[(uint64_t)j * A.slots + s] < doc ? 1 : 0;
   }
   A.flags[i] = hit;
 }
