@@ -78,6 +78,33 @@ LB_FN uint32_t perm_lo32(uint32_t x, uint32_t a_lo, uint32_t a_hi, uint32_t b_lo
   return (uint32_t)R + (uint32_t)((R + 1) >> 61);
 }
 
+// The low word of R above, in three 32x32+64 multiply-adds, plus a word that
+// flags the rare R >= p.  The high coefficient words come times 8
+// (a_hi8 = 8 a_hi, b_hi8 = 8 b_hi, both below 2^32 as a_hi, b_hi < 2^29):
+//   S = a_hi8 * x + b_hi8 + 8 * (P >> 32) = 8 Q   (< 2^64 as Q < 2^61),
+// so S >> 32 = Q >> 29 and low32(S) = 8 (Q mod 2^29), and
+//   low32(R) = low32(P) + (S >> 32).
+// R >= p needs Q mod 2^29 >= 2^29 - 2, i.e. flag = low32(S) >= 2^32 - 16:
+// otherwise R <= (2^29 - 3) 2^32 + 2 (2^32 - 1) < 2^61 - 1.  A caller that
+// finds no flag at or above kPermFlag has the canonical low words; otherwise
+// it recomputes with perm_lo32 (about 2^-28 of evaluations).
+constexpr uint32_t kPermFlag = 0xFFFFFFF0u;
+
+LB_FN uint32_t perm_lo32_flagged(uint32_t x, uint32_t a_lo, uint32_t a_hi8, uint32_t b_lo, uint32_t b_hi8,
+                                 uint32_t &flag) {
+  const uint64_t P = (uint64_t)a_lo * x + b_lo;
+  uint32_t eight = 8;
+#if defined(__HIP_DEVICE_COMPILE__)
+  // An opaque 8 in a scalar register: the product below then stays one
+  // v_mad_u64_u32 that reads the high word of P in place, where a constant
+  // would become a 64-bit shift of a register pair built by an extra move.
+  asm("" : "+s"(eight));
+#endif
+  const uint64_t S = (uint64_t)(uint32_t)(P >> 32) * eight + ((uint64_t)a_hi8 * x + b_hi8);
+  flag = (uint32_t)S;
+  return (uint32_t)P + (uint32_t)(S >> 32);
+}
+
 // Three-input bitwise functions of SHA-1 (FIPS 180-4 §4.1.1).  On gfx950 each
 // is one v_bitop3_b32 (truth tables 0x96 = x^y^z, 0xE8 = majority; both are
 // symmetric, so the operand order does not matter).

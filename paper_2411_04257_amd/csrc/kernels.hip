@@ -63,6 +63,14 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
   return (int64_t)(((uint64_t)rhi << 32) | rlo);
 }
 
+// Lane src's value of v in scalar registers: known wave-uniform, so that
+// branches on it and values derived from it stay off the vector registers.
+__device__ __forceinline__ int64_t readlane64(int64_t v, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(uint64_t)v, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), src);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // Waves per SIMD the register budget must allow (97 VGPRs would give 4 at
 // PPL = 2; 96 gives 5).
 constexpr int minhash_min_waves(int ppl) { return ppl <= 2 ? 5 : (ppl <= 4 ? 4 : 3); }
@@ -74,7 +82,10 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
   using V = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   constexpr V kEmpty = ~(V)0;
   const int lane = threadIdx.x & 63;
-  const int64_t wave = (int64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+  // The wave's index, its token range and the tile positions derived from it
+  // are wave-uniform: readfirstlane keeps them in scalar registers.
+  const int64_t wave =
+      (int64_t)blockIdx.x * (kBlock / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const int64_t n_docs = A.n_docs;
   const int64_t base = A.offsets[0];
   const int64_t end = A.offsets[n_docs];
@@ -93,10 +104,11 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
     const uint32_t i = (uint32_t)p * 64u + (uint32_t)lane;
     PermCoef c = {0, 0, 0, 0};
     if (i < P) c = A.coef[i];
+    // The 32-bit path keeps the high words times 8 (perm_lo32_flagged).
     al[p] = c.a_lo;
-    ah[p] = c.a_hi;
+    ah[p] = WIDE ? c.a_hi : c.a_hi << 3;
     bl[p] = c.b_lo;
-    bh[p] = c.b_hi;
+    bh[p] = WIDE ? c.b_hi : c.b_hi << 3;
     mn[p] = kEmpty;
   }
 
@@ -143,7 +155,7 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
     // Ends of documents dcur, dcur+1, ..., dcur+63.
     const int64_t jd = dcur + 1 + lane;
     const int64_t e = (jd <= n_docs) ? A.offsets[jd] : INT64_MAX;
-    const int64_t e63 = shfl64(e, 63);
+    const int64_t e63 = readlane64(e, 63);
     int64_t doc, ds, de, dnext;
     if (e63 > tb + 64) {
       // The 64-document window covers the tile: count the ends <= pos.
@@ -224,26 +236,25 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
           for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], min(c0[p], c1[p]));
           continue;
         }
-        // Common path: the Mersenne-folded R without its canonical
-        // correction, plus one compare per evaluation whose lane mask is
-        // OR-ed on the scalar unit.  R >= p (probability ~2^-29 per
-        // evaluation) sends the wave through the correction.
-        uint64_t R0[PPL], R1[PPL];
+        // Common path: the low words of the Mersenne-folded R without the
+        // canonical correction, and one flag word per evaluation whose
+        // maximum is tested once.  A flag at or above kPermFlag (about 2^-28
+        // per evaluation, a superset of R >= p) sends the wave through the
+        // exact form for all its evaluations.
         uint32_t v0[PPL], v1[PPL];
-        uint64_t ge = 0;
+        uint32_t fmax = 0;
 #pragma unroll
         for (int p = 0; p < PPL; ++p) {
-          R0[p] = perm_r(x0, al[p], ah[p], bl[p], bh[p]);
-          R1[p] = perm_r(x1, al[p], ah[p], bl[p], bh[p]);
-          v0[p] = (uint32_t)R0[p];
-          v1[p] = (uint32_t)R1[p];
-          ge |= __ballot(R0[p] >= kP61) | __ballot(R1[p] >= kP61);
+          uint32_t f0, f1;
+          v0[p] = perm_lo32_flagged(x0, al[p], ah[p], bl[p], bh[p], f0);
+          v1[p] = perm_lo32_flagged(x1, al[p], ah[p], bl[p], bh[p], f1);
+          fmax = max(fmax, max(f0, f1));
         }
-        if (ge) {
+        if (__ballot(fmax >= kPermFlag)) {
 #pragma unroll
           for (int p = 0; p < PPL; ++p) {
-            v0[p] += (uint32_t)((R0[p] + 1) >> 61);
-            v1[p] += (uint32_t)((R1[p] + 1) >> 61);
+            v0[p] = perm_lo32(x0, al[p], ah[p] >> 3, bl[p], bh[p] >> 3);
+            v1[p] = perm_lo32(x1, al[p], ah[p] >> 3, bl[p], bh[p] >> 3);
           }
         }
 #pragma unroll

@@ -115,6 +115,9 @@ extern "C" {
 uint32_t h_perm(uint32_t x, uint64_t a, uint64_t b) {
   return lb::perm_lo32(x, (uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
 }
+uint32_t h_perm_flagged(uint32_t x, uint64_t a, uint64_t b, uint32_t* flag) {
+  return lb::perm_lo32_flagged(x, (uint32_t)a, (uint32_t)(a >> 32) << 3, (uint32_t)b, (uint32_t)(b >> 32) << 3, *flag);
+}
 uint32_t h_shingle5(const uint32_t* t) { return lb::shingle_hash_fixed<5>(t); }
 uint32_t h_shingle(const uint32_t* t, uint32_t n) { return lb::shingle_hash_var(t, n); }
 uint64_t h_band_key(const uint32_t* row, uint32_t r, uint64_t salt) { return lb::band_key(row, r, salt); }
@@ -134,6 +137,8 @@ def harness(tmp_path_factory):
     L = ctypes.CDLL(str(so))
     L.h_perm.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64]
     L.h_perm.restype = ctypes.c_uint32
+    L.h_perm_flagged.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
+    L.h_perm_flagged.restype = ctypes.c_uint32
     L.h_shingle5.argtypes = [ctypes.c_void_p]
     L.h_shingle5.restype = ctypes.c_uint32
     L.h_shingle.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
@@ -159,6 +164,36 @@ def test_device_perm_matches_big_integers(harness):
         cases.append((int(rng.integers(0, 2**32)), int(rng.integers(1, P61)), int(rng.integers(0, P61))))
     for x, a, b in cases:
         assert harness.h_perm(x, a, b) == ((a * x + b) % P61) & 0xFFFFFFFF, (x, a, b)
+
+
+def test_device_flagged_perm_is_exact_unless_flagged(harness):
+    """The three-multiply form returns the canonical low word whenever its
+    flag stays below 2^32 - 16, and raises the flag on every input whose
+    Mersenne-folded value needs the final subtraction of p (inputs built so
+    that a*x + b's folded form lands on or above p)."""
+    flag = ctypes.c_uint32()
+    rng = np.random.default_rng(5)
+    M32 = 0xFFFFFFFF
+    cases = [(x, a, b) for x in (0, 1, 2**32 - 1) for a in (1, P61 - 1, 2**32 - 1) for b in (0, 1, P61 - 1)]
+    for _ in range(60_000):
+        cases.append((int(rng.integers(0, 2**32)), int(rng.integers(1, P61)), int(rng.integers(0, P61))))
+    # b's high word chosen so that the folded value's high part is all ones
+    # (Q mod 2^29 = 2^29 - 1), where the subtraction is usually needed
+    for _ in range(20_000):
+        x, a, bl = int(rng.integers(0, 2**32)), int(rng.integers(1, P61)), int(rng.integers(0, 2**32 - 1))
+        p_hi = ((a & M32) * x + bl) >> 32
+        bh = (2**29 - 1 - (a >> 32) * x - p_hi) % 2**29
+        cases.append((x, a, (bh << 32) | bl))
+    flagged = wrong = 0
+    for x, a, b in cases:
+        v = harness.h_perm_flagged(x, a, b, ctypes.byref(flag))
+        exact = ((a * x + b) % P61) & M32
+        if flag.value >= 0xFFFFFFF0:
+            flagged += 1
+            wrong += v != exact
+        else:
+            assert v == exact, (x, a, b)
+    assert wrong > 2_000 and flagged < 25_000
 
 
 def test_device_shingle_hash_matches_hashlib(harness):

@@ -468,9 +468,11 @@ def test_c2_full_batch_prefix_and_samples(gpu, qi_mode):
 
 def test_minhash_rare_canonical_correction(gpu):
     """The MinHash kernel skips the canonical correction of the Mersenne fold
-    unless some lane's folded value is >= 2^61-1 (about 2^-29 per
-    evaluation).  Search single-token shingles and index seeds for cases that
-    take that path, then check those documents bit for bit."""
+    unless some lane's flag says the folded value may be >= 2^61-1: the fold's
+    high part Q mod 2^29 is 2^29-2 or 2^29-1 (about 2^-28 per evaluation).
+    Search single-token shingles and index seeds for both kinds of flagged
+    evaluation, those whose folded value does reach p and those whose does
+    not, then check those documents bit for bit."""
     import hashlib
 
     P61 = (1 << 61) - 1
@@ -480,7 +482,7 @@ def test_minhash_rare_canonical_correction(gpu):
                        dtype="<u4").astype(np.int64)
     xg = torch.as_tensor(xs, device="cuda")
     M32 = 0xFFFFFFFF
-    found = []
+    over, flag_only = [], []
     for seed in range(1, 65):
         a, b, _ = oracle.OracleIndex(128, 16, 8, 1000, 1e-3, seed, 1).coeffs()
         for i in range(128):
@@ -490,14 +492,15 @@ def test_minhash_rare_canonical_correction(gpu):
             P_lo, P_hi = Pv & M32, (Pv >> 32) & M32
             Q = xg * ah + bh + P_hi
             R = (((Q & 0x1FFFFFFF) << 32) | P_lo) + (Q >> 29)
-            hit = torch.nonzero(R >= P61).flatten()
-            if hit.numel():
-                found += [(seed, int(t)) for t in hit.cpu().numpy()]
-        if len(found) >= 3:
+            flagged = (Q & 0x1FFFFFFF) >= (1 << 29) - 2
+            over += [(seed, int(t)) for t in torch.nonzero(R >= P61).flatten().cpu().numpy()]
+            flag_only += [(seed, int(t)) for t in torch.nonzero(flagged & (R < P61)).flatten().cpu().numpy()]
+        if len(over) >= 3 and len(flag_only) >= 2:
             break
-    assert found, "no evaluation needing the correction was found"
+    assert over and flag_only, "no evaluation taking the correction path was found"
+    found = over[:4] + flag_only[:2]
     rng = np.random.default_rng(21)
-    for seed, tok in found[:4]:
+    for seed, tok in found:
         docs = [[tok], rng.integers(0, n_tok, 50).tolist() + [tok] + rng.integers(0, n_tok, 50).tolist(),
                 [tok] * 3, rng.integers(0, n_tok, 200).tolist()]
         off, tk = _csr(docs)
