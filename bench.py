@@ -29,18 +29,18 @@ if ROOT not in sys.path:
 
 # Per-unit VALU lane-operation counts of the MinHash hot loops (gfx950 ISA of
 # k_minhash<PPL=2, w=5>): one SHA-1 shingle hash of a 5-token shingle (573),
-# and one exact (a*x+b) mod (2^61-1) evaluation with its share of the running
-# min and of the flag test (3 v_mad_u64_u32 + 1 add, 1/2 of a v_min3 shared by
-# two shingles, and 3/4 for the max3/max/compare over the flags of four
-# evaluations: 21 instructions per 4 evaluations).
+# and one exact (a*x+b) mod (2^61-1) evaluation in a full 64-shingle tile with
+# its share of the running min and of the flag test (3 v_mad_u64_u32 + 1 add,
+# 1/2 of a v_min3 and 1/2 of a v_max3, each folding two evaluations: 80
+# instructions per 16 evaluations).
 OPS_PER_SHINGLE_HASH = 573
-OPS_PER_SHINGLE_PERM = 5.25
+OPS_PER_SHINGLE_PERM = 5.0
 INT32_VALU_PEAK = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
 # HBM bytes per token that k_minhash moved, from rocprofv3 FETCH_SIZE (x2.0) and
 # WRITE_SIZE (x1.0) scaled by a 1 GiB copy (profiles/k_minhash_c2_counters.md):
-# 1.1735e9 B for a 2.717e8-token batch (65,536 waves).  Valid for the kernel
+# 1.1747e9 B for a 2.717e8-token batch (65,536 waves).  Valid for the kernel
 # version and grid sizing profiled.
-MINHASH_HBM_BYTES_PER_TOKEN = 1.1735e9 / 2.7175e8
+MINHASH_HBM_BYTES_PER_TOKEN = 1.1747e9 / 2.7175e8
 
 
 def parse():

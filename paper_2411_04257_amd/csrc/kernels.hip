@@ -63,6 +63,15 @@ __device__ __forceinline__ int64_t shfl64(int64_t v, int src) {
   return (int64_t)(((uint64_t)rhi << 32) | rlo);
 }
 
+// Orders one wave's LDS accesses around an exchange between its lanes: a
+// wave's LDS operations complete in issue order, so only the compiler needs
+// holding back.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Lane src's value of v in scalar registers: known wave-uniform, so that
 // branches on it and values derived from it stay off the vector registers.
 __device__ __forceinline__ int64_t readlane64(int64_t v, int src) {
@@ -82,6 +91,9 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
   using V = typename std::conditional<WIDE, uint64_t, uint32_t>::type;
   constexpr V kEmpty = ~(V)0;
   const int lane = threadIdx.x & 63;
+  // The wave's row of shingle hashes for the full-tile path.
+  __shared__ __align__(16) uint32_t xs_block[kBlock];
+  uint32_t *const xs = xs_block + (threadIdx.x & ~63u);
   // The wave's index, its token range and the tile positions derived from it
   // are wave-uniform: readfirstlane keeps them in scalar registers.
   const int64_t wave =
@@ -149,39 +161,101 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
     }
   };
 
+  // A tile of 64 shingles of document d, lane i holding shingle i's hash.
+  // The hashes go through the wave's LDS row and come back as uniform-address
+  // 16-byte reads, broadcasts on the LDS pipe instead of one VALU readlane
+  // per shingle.  The flag words of the whole tile fold into one maximum,
+  // tested once; a flagged tile restarts from the minima saved at its start
+  // and takes the exact form for all its evaluations.
+  auto full_tile = [&](int64_t d, uint32_t x) {
+    if (d != cur) {
+      if (cur >= 0) flush(cur);
+      cur = d;
+    }
+    wave_lds_sync();
+    xs[lane] = x;
+    wave_lds_sync();
+    V saved[PPL];
+#pragma unroll
+    for (int p = 0; p < PPL; ++p) saved[p] = mn[p];
+    uint32_t fmax = 0;
+#pragma unroll 2
+    for (int k = 0; k < 64; k += 4) {
+      const uint4 q = *reinterpret_cast<const uint4 *>(xs + k);
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) {
+        uint32_t f0, f1, f2, f3;
+        const uint32_t v0 = perm_lo32_flagged(q.x, al[p], ah[p], bl[p], bh[p], f0);
+        const uint32_t v1 = perm_lo32_flagged(q.y, al[p], ah[p], bl[p], bh[p], f1);
+        const uint32_t v2 = perm_lo32_flagged(q.z, al[p], ah[p], bl[p], bh[p], f2);
+        const uint32_t v3 = perm_lo32_flagged(q.w, al[p], ah[p], bl[p], bh[p], f3);
+        // chains, so that each folds into two v_min3 / v_max3
+        mn[p] = min(min(min(min(mn[p], v0), v1), v2), v3);
+        fmax = max(max(max(max(fmax, f0), f1), f2), f3);
+      }
+    }
+    if (__ballot(fmax >= kPermFlag)) {
+#pragma unroll
+      for (int p = 0; p < PPL; ++p) mn[p] = saved[p];
+      for (int k = 0; k < 64; ++k) {
+        const uint32_t xk = xs[k];
+#pragma unroll
+        for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], perm_lo32(xk, al[p], ah[p] >> 3, bl[p], bh[p] >> 3));
+      }
+    }
+  };
+
   for (int64_t tb = r0; tb < r1; tb += 64) {
     const int64_t pos = tb + lane;
-    const bool in_range = pos < r1;
-    // Ends of documents dcur, dcur+1, ..., dcur+63.
-    const int64_t jd = dcur + 1 + lane;
-    const int64_t e = (jd <= n_docs) ? A.offsets[jd] : INT64_MAX;
-    const int64_t e63 = readlane64(e, 63);
     int64_t doc, ds, de, dnext;
-    if (e63 > tb + 64) {
-      // The 64-document window covers the tile: count the ends <= pos.
-      int lo = 0;
-#pragma unroll
-      for (int step = 32; step >= 1; step >>= 1) {
-        const int64_t v = shfl64(e, lo + step - 1);
-        if (v <= pos) lo += step;
-      }
-      doc = dcur + lo;
-      de = shfl64(e, lo);
-      const int64_t prev = shfl64(e, lo > 0 ? lo - 1 : 0);
-      ds = lo > 0 ? prev : A.offsets[dcur];
-      dnext = dcur + __popcll(__ballot(e <= tb + 64));
+    bool valid;
+    // Tile inside the current document: its end, one scalar load, covers the
+    // last lane's shingle (and the next tile starts in it too), so every lane
+    // holds a shingle of document dcur and the search is skipped.  ds = tb
+    // stands in for the document's start (only L >= w is read from it).
+    bool inside_doc = false;
+    if constexpr (!WIDE) {
+      de = A.offsets[dcur + 1];
+      inside_doc = tb + 64 <= r1 && de >= tb + 63 + (w > 2 ? w : 2);
+    }
+    if (inside_doc) {
+      doc = dcur;
+      ds = tb;
+      dnext = dcur;
+      valid = true;
     } else {
-      // More than 63 documents end inside the tile (empty documents):
-      // search the whole offsets array.
-      doc = upper_bound_i64(A.offsets, n_docs + 1, pos) - 1;
-      if (doc > n_docs - 1) doc = n_docs - 1;
-      ds = A.offsets[doc];
-      de = A.offsets[doc + 1];
-      dnext = upper_bound_i64(A.offsets, n_docs + 1, tb + 64) - 1;
-      if (dnext > n_docs) dnext = n_docs;
+      const bool in_range = pos < r1;
+      // Ends of documents dcur, dcur+1, ..., dcur+63.
+      const int64_t jd = dcur + 1 + lane;
+      const int64_t e = (jd <= n_docs) ? A.offsets[jd] : INT64_MAX;
+      const int64_t e63 = readlane64(e, 63);
+      if (e63 > tb + 64) {
+        // The 64-document window covers the tile: count the ends <= pos.
+        int lo = 0;
+#pragma unroll
+        for (int step = 32; step >= 1; step >>= 1) {
+          const int64_t v = shfl64(e, lo + step - 1);
+          if (v <= pos) lo += step;
+        }
+        doc = dcur + lo;
+        de = shfl64(e, lo);
+        const int64_t prev = shfl64(e, lo > 0 ? lo - 1 : 0);
+        ds = lo > 0 ? prev : A.offsets[dcur];
+        dnext = dcur + __popcll(__ballot(e <= tb + 64));
+      } else {
+        // More than 63 documents end inside the tile (empty documents):
+        // search the whole offsets array.
+        doc = upper_bound_i64(A.offsets, n_docs + 1, pos) - 1;
+        if (doc > n_docs - 1) doc = n_docs - 1;
+        ds = A.offsets[doc];
+        de = A.offsets[doc + 1];
+        dnext = upper_bound_i64(A.offsets, n_docs + 1, tb + 64) - 1;
+        if (dnext > n_docs) dnext = n_docs;
+      }
+      const int64_t L = de - ds;
+      valid = in_range && pos >= ds && pos < de && L > 0 && ((L >= w) ? (pos <= de - w) : (pos == ds));
     }
     const int64_t L = de - ds;
-    const bool valid = in_range && pos >= ds && pos < de && L > 0 && ((L >= w) ? (pos <= de - w) : (pos == ds));
     uint32_t x = 0;
     if (valid) {
       const uint32_t *tp = A.tokens + pos + (A.tok_shift ? A.tok_shift[doc] : 0);
@@ -190,9 +264,21 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
       else
         x = shingle_hash_var(tp, (uint32_t)(L >= w ? w : L));
     }
+    if (inside_doc) {
+      full_tile(dcur, x);
+      continue;
+    }
     const int32_t drel = (int32_t)(doc - dcur);
 
     uint64_t vm = __ballot(valid);
+    if constexpr (!WIDE) {
+      // Full tile found by the search: 64 shingles of one document
+      // (documents ascend with the lane, so the first and last lane decide).
+      if (vm == ~0ull && __builtin_amdgcn_readlane(drel, 0) == __builtin_amdgcn_readlane(drel, 63)) {
+        full_tile(dcur + __builtin_amdgcn_readlane(drel, 0), x);
+        vm = 0;
+      }
+    }
     while (vm) {
       const int s = __ffsll((unsigned long long)vm) - 1;
       const int32_t dr = __builtin_amdgcn_readlane(drel, s);

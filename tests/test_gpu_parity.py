@@ -501,8 +501,12 @@ def test_minhash_rare_canonical_correction(gpu):
     found = over[:4] + flag_only[:2]
     rng = np.random.default_rng(21)
     for seed, tok in found:
+        # the last document is long enough that the token lands in full
+        # 64-shingle tiles, whose flag test covers the whole tile
+        long_doc = rng.integers(0, n_tok, 6000)
+        long_doc[[70, 1500, 1501, 3333, 5990]] = tok
         docs = [[tok], rng.integers(0, n_tok, 50).tolist() + [tok] + rng.integers(0, n_tok, 50).tolist(),
-                [tok] * 3, rng.integers(0, n_tok, 200).tolist()]
+                [tok] * 3, rng.integers(0, n_tok, 200).tolist(), long_doc.tolist()]
         off, tk = _csr(docs)
         g = gpu.LSHBloom(128, 16, 8, 1000, 1e-3, seed, shingle_width=1)
         o = oracle.OracleIndex(128, 16, 8, 1000, 1e-3, seed, 1)
