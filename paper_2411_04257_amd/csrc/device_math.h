@@ -105,6 +105,26 @@ LB_FN uint32_t perm_lo32_flagged(uint32_t x, uint32_t a_lo, uint32_t a_hi8, uint
   return (uint32_t)P + (uint32_t)(S >> 32);
 }
 
+// The whole folded R of perm_r (not yet reduced below p) from the same three
+// multiply-adds: Q mod 2^29 = low32(S) >> 3 and Q >> 29 = S >> 32, so
+//   R = (low32(S) >> 3) * 2^32 + low32(P) + (S >> 32),
+// with the same flag word: no flag at or above kPermFlag means R < p.
+LB_FN uint64_t perm_r_flagged(uint32_t x, uint32_t a_lo, uint32_t a_hi8, uint32_t b_lo, uint32_t b_hi8,
+                              uint32_t &flag) {
+  const uint64_t P = (uint64_t)a_lo * x + b_lo;
+  uint32_t eight = 8;
+#if defined(__HIP_DEVICE_COMPILE__)
+  asm("" : "+s"(eight));  // as in perm_lo32_flagged
+#endif
+  const uint64_t S = (uint64_t)(uint32_t)(P >> 32) * eight + ((uint64_t)a_hi8 * x + b_hi8);
+  flag = (uint32_t)S;
+  // two 32-bit halves with one carry, not a 64-bit sum of register pairs
+  const uint32_t s_hi = (uint32_t)(S >> 32);
+  const uint32_t r_lo = (uint32_t)P + s_hi;
+  const uint32_t r_hi = ((uint32_t)S >> 3) + (r_lo < s_hi ? 1u : 0u);
+  return ((uint64_t)r_hi << 32) | r_lo;
+}
+
 // Three-input bitwise functions of SHA-1 (FIPS 180-4 §4.1.1).  On gfx950 each
 // is one v_bitop3_b32 (truth tables 0x96 = x^y^z, 0xE8 = majority; both are
 // symmetric, so the operand order does not matter).

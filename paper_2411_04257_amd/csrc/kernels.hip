@@ -116,11 +116,11 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
     const uint32_t i = (uint32_t)p * 64u + (uint32_t)lane;
     PermCoef c = {0, 0, 0, 0};
     if (i < P) c = A.coef[i];
-    // The 32-bit path keeps the high words times 8 (perm_lo32_flagged).
+    // The high words are kept times 8 (perm_lo32_flagged, perm_r_flagged).
     al[p] = c.a_lo;
-    ah[p] = WIDE ? c.a_hi : c.a_hi << 3;
+    ah[p] = c.a_hi << 3;
     bl[p] = c.b_lo;
-    bh[p] = WIDE ? c.b_hi : c.b_hi << 3;
+    bh[p] = c.b_hi << 3;
     mn[p] = kEmpty;
   }
 
@@ -185,12 +185,21 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
 #pragma unroll
       for (int p = 0; p < PPL; ++p) {
         uint32_t f0, f1, f2, f3;
-        const uint32_t v0 = perm_lo32_flagged(q.x, al[p], ah[p], bl[p], bh[p], f0);
-        const uint32_t v1 = perm_lo32_flagged(q.y, al[p], ah[p], bl[p], bh[p], f1);
-        const uint32_t v2 = perm_lo32_flagged(q.z, al[p], ah[p], bl[p], bh[p], f2);
-        const uint32_t v3 = perm_lo32_flagged(q.w, al[p], ah[p], bl[p], bh[p], f3);
-        // chains, so that each folds into two v_min3 / v_max3
-        mn[p] = min(min(min(min(mn[p], v0), v1), v2), v3);
+        if constexpr (WIDE) {
+          // folded values not yet below p: a flag-free tile has them all < p
+          const uint64_t c0 = perm_r_flagged(q.x, al[p], ah[p], bl[p], bh[p], f0);
+          const uint64_t c1 = perm_r_flagged(q.y, al[p], ah[p], bl[p], bh[p], f1);
+          const uint64_t c2 = perm_r_flagged(q.z, al[p], ah[p], bl[p], bh[p], f2);
+          const uint64_t c3 = perm_r_flagged(q.w, al[p], ah[p], bl[p], bh[p], f3);
+          mn[p] = min(min(min(min(mn[p], c0), c1), c2), c3);
+        } else {
+          const uint32_t v0 = perm_lo32_flagged(q.x, al[p], ah[p], bl[p], bh[p], f0);
+          const uint32_t v1 = perm_lo32_flagged(q.y, al[p], ah[p], bl[p], bh[p], f1);
+          const uint32_t v2 = perm_lo32_flagged(q.z, al[p], ah[p], bl[p], bh[p], f2);
+          const uint32_t v3 = perm_lo32_flagged(q.w, al[p], ah[p], bl[p], bh[p], f3);
+          // chains, so that each folds into two v_min3 / v_max3
+          mn[p] = min(min(min(min(mn[p], v0), v1), v2), v3);
+        }
         fmax = max(max(max(max(fmax, f0), f1), f2), f3);
       }
     }
@@ -200,7 +209,15 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
       for (int k = 0; k < 64; ++k) {
         const uint32_t xk = xs[k];
 #pragma unroll
-        for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], perm_lo32(xk, al[p], ah[p] >> 3, bl[p], bh[p] >> 3));
+        for (int p = 0; p < PPL; ++p) {
+          if constexpr (WIDE) {
+            uint32_t f;
+            const uint64_t c = perm_r_flagged(xk, al[p], ah[p], bl[p], bh[p], f);
+            mn[p] = min(mn[p], c >= kP61 ? c - kP61 : c);
+          } else {
+            mn[p] = min(mn[p], perm_lo32(xk, al[p], ah[p] >> 3, bl[p], bh[p] >> 3));
+          }
+        }
       }
     }
   };
@@ -213,11 +230,8 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
     // last lane's shingle (and the next tile starts in it too), so every lane
     // holds a shingle of document dcur and the search is skipped.  ds = tb
     // stands in for the document's start (only L >= w is read from it).
-    bool inside_doc = false;
-    if constexpr (!WIDE) {
-      de = A.offsets[dcur + 1];
-      inside_doc = tb + 64 <= r1 && de >= tb + 63 + (w > 2 ? w : 2);
-    }
+    de = A.offsets[dcur + 1];
+    const bool inside_doc = tb + 64 <= r1 && de >= tb + 63 + (w > 2 ? w : 2);
     if (inside_doc) {
       doc = dcur;
       ds = tb;
@@ -271,13 +285,11 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
     const int32_t drel = (int32_t)(doc - dcur);
 
     uint64_t vm = __ballot(valid);
-    if constexpr (!WIDE) {
-      // Full tile found by the search: 64 shingles of one document
-      // (documents ascend with the lane, so the first and last lane decide).
-      if (vm == ~0ull && __builtin_amdgcn_readlane(drel, 0) == __builtin_amdgcn_readlane(drel, 63)) {
-        full_tile(dcur + __builtin_amdgcn_readlane(drel, 0), x);
-        vm = 0;
-      }
+    // Full tile found by the search: 64 shingles of one document (documents
+    // ascend with the lane, so the first and last lane decide).
+    if (vm == ~0ull && __builtin_amdgcn_readlane(drel, 0) == __builtin_amdgcn_readlane(drel, 63)) {
+      full_tile(dcur + __builtin_amdgcn_readlane(drel, 0), x);
+      vm = 0;
     }
     while (vm) {
       const int s = __ffsll((unsigned long long)vm) - 1;
@@ -302,16 +314,17 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
         const uint32_t x1 = __builtin_amdgcn_readlane(x, s1);
         if constexpr (WIDE) {
           // the canonical value: R < 2p needs one conditional subtraction,
-          // taken (as below for 32-bit values) only when some lane has R >= p
+          // taken only when some lane's flag says R may be >= p
           uint64_t c0[PPL], c1[PPL];
-          uint64_t ge = 0;
+          uint32_t fmax = 0;
 #pragma unroll
           for (int p = 0; p < PPL; ++p) {
-            c0[p] = perm_r(x0, al[p], ah[p], bl[p], bh[p]);
-            c1[p] = perm_r(x1, al[p], ah[p], bl[p], bh[p]);
-            ge |= __ballot(c0[p] >= kP61) | __ballot(c1[p] >= kP61);
+            uint32_t f0, f1;
+            c0[p] = perm_r_flagged(x0, al[p], ah[p], bl[p], bh[p], f0);
+            c1[p] = perm_r_flagged(x1, al[p], ah[p], bl[p], bh[p], f1);
+            fmax = max(max(fmax, f0), f1);
           }
-          if (ge) {
+          if (__ballot(fmax >= kPermFlag)) {
 #pragma unroll
             for (int p = 0; p < PPL; ++p) {
               c0[p] = c0[p] >= kP61 ? c0[p] - kP61 : c0[p];

@@ -118,6 +118,9 @@ uint32_t h_perm(uint32_t x, uint64_t a, uint64_t b) {
 uint32_t h_perm_flagged(uint32_t x, uint64_t a, uint64_t b, uint32_t* flag) {
   return lb::perm_lo32_flagged(x, (uint32_t)a, (uint32_t)(a >> 32) << 3, (uint32_t)b, (uint32_t)(b >> 32) << 3, *flag);
 }
+uint64_t h_perm61_flagged(uint32_t x, uint64_t a, uint64_t b, uint32_t* flag) {
+  return lb::perm_r_flagged(x, (uint32_t)a, (uint32_t)(a >> 32) << 3, (uint32_t)b, (uint32_t)(b >> 32) << 3, *flag);
+}
 uint32_t h_shingle5(const uint32_t* t) { return lb::shingle_hash_fixed<5>(t); }
 uint32_t h_shingle(const uint32_t* t, uint32_t n) { return lb::shingle_hash_var(t, n); }
 uint64_t h_band_key(const uint32_t* row, uint32_t r, uint64_t salt) { return lb::band_key(row, r, salt); }
@@ -139,6 +142,8 @@ def harness(tmp_path_factory):
     L.h_perm.restype = ctypes.c_uint32
     L.h_perm_flagged.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
     L.h_perm_flagged.restype = ctypes.c_uint32
+    L.h_perm61_flagged.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
+    L.h_perm61_flagged.restype = ctypes.c_uint64
     L.h_shingle5.argtypes = [ctypes.c_void_p]
     L.h_shingle5.restype = ctypes.c_uint32
     L.h_shingle.argtypes = [ctypes.c_void_p, ctypes.c_uint32]
@@ -167,10 +172,11 @@ def test_device_perm_matches_big_integers(harness):
 
 
 def test_device_flagged_perm_is_exact_unless_flagged(harness):
-    """The three-multiply form returns the canonical low word whenever its
-    flag stays below 2^32 - 16, and raises the flag on every input whose
-    Mersenne-folded value needs the final subtraction of p (inputs built so
-    that a*x + b's folded form lands on or above p)."""
+    """The three-multiply forms return the canonical low word (and the whole
+    canonical 61-bit value) whenever their flag stays below 2^32 - 16, and
+    raise the flag on every input whose Mersenne-folded value needs the final
+    subtraction of p (inputs built so that a*x + b's folded form lands on or
+    above p)."""
     flag = ctypes.c_uint32()
     rng = np.random.default_rng(5)
     M32 = 0xFFFFFFFF
@@ -187,12 +193,19 @@ def test_device_flagged_perm_is_exact_unless_flagged(harness):
     flagged = wrong = 0
     for x, a, b in cases:
         v = harness.h_perm_flagged(x, a, b, ctypes.byref(flag))
-        exact = ((a * x + b) % P61) & M32
+        exact61 = (a * x + b) % P61
+        exact = exact61 & M32
         if flag.value >= 0xFFFFFFF0:
             flagged += 1
             wrong += v != exact
         else:
             assert v == exact, (x, a, b)
+        # the whole folded value: congruent to a*x + b, below 2p, and below p
+        # (so canonical) whenever the same flag stays low
+        r = harness.h_perm61_flagged(x, a, b, ctypes.byref(flag))
+        assert r % P61 == exact61 and r < 2 * P61, (x, a, b)
+        if flag.value < 0xFFFFFFF0:
+            assert r == exact61, (x, a, b)
     assert wrong > 2_000 and flagged < 25_000
 
 

@@ -130,9 +130,12 @@ def test_keys_path_rejects_bad_arguments(gpu):
 
 def test_minhash61_rare_canonical_correction(gpu):
     """The wide kernel, like the 32-bit one, subtracts p only when some
-    lane's folded value R is >= 2^61 - 1 (about 2^-29 per evaluation).
-    Single-token shingles and index seeds that reach that path are found by
-    evaluating R for 2^20 tokens, then checked bit for bit."""
+    lane's flag says the folded value R may be >= 2^61 - 1 (its high part
+    Q mod 2^29 is 2^29 - 2 or 2^29 - 1, about 2^-28 per evaluation).
+    Single-token shingles and index seeds giving both kinds of flagged
+    evaluation (R >= p, and R < p) are found by evaluating R for 2^20 tokens,
+    then checked bit for bit, also inside full 64-shingle tiles of a long
+    document."""
     import hashlib
 
     P61 = (1 << 61) - 1
@@ -142,7 +145,7 @@ def test_minhash61_rare_canonical_correction(gpu):
                        dtype="<u4").astype(np.int64)
     xg = torch.as_tensor(xs, device="cuda")
     M32 = 0xFFFFFFFF
-    found = []
+    over, flag_only = [], []
     for seed in range(1, 65):
         a, b, _ = oracle.OracleIndex(128, 16, 8, 1000, 1e-3, seed, 1).coeffs()
         for i in range(128):
@@ -152,15 +155,18 @@ def test_minhash61_rare_canonical_correction(gpu):
             P_lo, P_hi = Pv & M32, (Pv >> 32) & M32
             Q = xg * ah + bh + P_hi
             R = (((Q & 0x1FFFFFFF) << 32) | P_lo) + (Q >> 29)
-            hit = torch.nonzero(R >= P61).flatten()
-            if hit.numel():
-                found += [(seed, int(t)) for t in hit.cpu().numpy()]
-        if len(found) >= 3:
+            flagged = (Q & 0x1FFFFFFF) >= (1 << 29) - 2
+            over += [(seed, int(t)) for t in torch.nonzero(R >= P61).flatten().cpu().numpy()]
+            flag_only += [(seed, int(t)) for t in torch.nonzero(flagged & (R < P61)).flatten().cpu().numpy()]
+        if len(over) >= 3 and len(flag_only) >= 2:
             break
-    assert found
+    assert over and flag_only
     rng = np.random.default_rng(22)
-    for seed, tok in found[:4]:
-        docs = [[tok], rng.integers(0, n_tok, 50).tolist() + [tok] + rng.integers(0, n_tok, 50).tolist(), [tok] * 3]
+    for seed, tok in over[:4] + flag_only[:2]:
+        long_doc = rng.integers(0, n_tok, 6000)
+        long_doc[[70, 1500, 1501, 3333, 5990]] = tok
+        docs = [[tok], rng.integers(0, n_tok, 50).tolist() + [tok] + rng.integers(0, n_tok, 50).tolist(), [tok] * 3,
+                long_doc.tolist()]
         off, tk = _csr(docs)
         g = gpu.LSHBloom(128, 16, 8, 1000, 1e-3, seed, shingle_width=1)
         o = oracle.OracleIndex(128, 16, 8, 1000, 1e-3, seed, 1)
