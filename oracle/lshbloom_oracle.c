@@ -32,6 +32,8 @@
  * Every function below states the passage or published definition it follows.
  */
 #include <math.h>
+#include <pthread.h>
+#include <stdatomic.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -340,6 +342,53 @@ int ora_minhash(const ora_index *h, const int64_t *offsets, const uint32_t *toke
     ora_minhash_doc(tokens + offsets[d], offsets[d + 1] - offsets[d], h->w, h->num_perm, h->a, h->b,
                     sigs + (uint64_t)d * h->num_perm);
   }
+  return 0;
+}
+
+/* The same MinHash with documents shared out over `threads` host threads:
+   every document is still the sequential per-document definition above
+   (ora_minhash_doc), and documents are independent (§2.2), so the output
+   equals ora_minhash's.  It exists to time the CPU path the way the paper's
+   own system runs it (MinHash parallel over documents, the filters
+   sequential, §4.4.2); ora_query_insert stays sequential. */
+typedef struct {
+  const ora_index *h;
+  const int64_t *offsets;
+  const uint32_t *tokens;
+  int64_t n_docs;
+  uint32_t *sigs;
+  atomic_llong next;
+} ora_mh_job;
+
+static void *ora_mh_worker(void *arg) {
+  ora_mh_job *j = (ora_mh_job *)arg;
+  for (;;) {
+    const int64_t d0 = (int64_t)atomic_fetch_add(&j->next, 16);
+    if (d0 >= j->n_docs) break;
+    const int64_t d1 = d0 + 16 < j->n_docs ? d0 + 16 : j->n_docs;
+    for (int64_t d = d0; d < d1; ++d)
+      ora_minhash_doc(j->tokens + j->offsets[d], j->offsets[d + 1] - j->offsets[d], j->h->w, j->h->num_perm,
+                      j->h->a, j->h->b, j->sigs + (uint64_t)d * j->h->num_perm);
+  }
+  return NULL;
+}
+
+int ora_minhash_threads(const ora_index *h, const int64_t *offsets, const uint32_t *tokens, int64_t n_docs,
+                        uint32_t *sigs, int threads) {
+  if (n_docs < 0 || threads < 1 || threads > 1024) return -1;
+  for (int64_t d = 0; d < n_docs; ++d)
+    if (offsets[d + 1] < offsets[d]) return -1;
+  ora_mh_job job = {h, offsets, tokens, n_docs, sigs, 0};
+  pthread_t *tid = (pthread_t *)calloc((size_t)threads, sizeof(pthread_t));
+  if (!tid) return -1;
+  int started = 0;
+  for (int t = 1; t < threads; ++t) {
+    if (pthread_create(&tid[t], NULL, ora_mh_worker, &job) != 0) break;
+    ++started;
+  }
+  ora_mh_worker(&job);
+  for (int t = 1; t <= started; ++t) pthread_join(tid[t], NULL);
+  free(tid);
   return 0;
 }
 

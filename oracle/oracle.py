@@ -28,7 +28,7 @@ def build(force: bool = False) -> str:
     """Compile the oracle into ``oracle/liblshbloom_oracle.so`` with gcc."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread", "-o", tmp, _SRC, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -72,6 +72,8 @@ def lib():
         L.ora_destroy.argtypes = [ctypes.c_void_p]
         L.ora_minhash.argtypes = [ctypes.c_void_p, _i64p, _u32p, ctypes.c_int64, _u32p]
         L.ora_minhash.restype = ctypes.c_int
+        L.ora_minhash_threads.argtypes = [ctypes.c_void_p, _i64p, _u32p, ctypes.c_int64, _u32p, ctypes.c_int]
+        L.ora_minhash_threads.restype = ctypes.c_int
         L.ora_perm61.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint32]
         L.ora_perm61.restype = ctypes.c_uint64
         L.ora_minhash_doc61.argtypes = [_u32p, ctypes.c_int64, ctypes.c_uint32, ctypes.c_uint32, _u64p, _u64p, _u64p]
@@ -245,6 +247,19 @@ class OracleIndex:
         rc = lib().ora_minhash(self._h, _ptr(offsets, ctypes.c_int64), tp, n, _ptr(sigs, ctypes.c_uint32))
         if rc != 0:
             raise ValueError("bad CSR batch")
+        return sigs
+
+    def minhash_threads(self, offsets: np.ndarray, tokens: np.ndarray, threads: int) -> np.ndarray:
+        """minhash() with documents shared out over host threads (same output)."""
+        offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+        tokens = np.ascontiguousarray(tokens, dtype=np.uint32)
+        n = len(offsets) - 1
+        sigs = np.zeros((max(n, 0), self.num_perm), np.uint32)
+        tp = _ptr(tokens, ctypes.c_uint32) if len(tokens) else _ptr(np.zeros(1, np.uint32), ctypes.c_uint32)
+        rc = lib().ora_minhash_threads(self._h, _ptr(offsets, ctypes.c_int64), tp, n, _ptr(sigs, ctypes.c_uint32),
+                                       int(threads))
+        if rc != 0:
+            raise ValueError("bad CSR batch or thread count")
         return sigs
 
     def query_insert(self, sigs: np.ndarray) -> np.ndarray:

@@ -130,6 +130,23 @@ def test_minhash_invariant_to_shingle_order_and_repeats():
     assert np.array_equal(s1, oracle.minhash_doc(doubled, 1, a, b))
 
 
+def test_threaded_minhash_equals_sequential():
+    """The host-threaded MinHash (used only to time the CPU path with all
+    cores) returns the sequential oracle's signatures for every thread
+    count, including empty and ragged documents."""
+    rng = np.random.default_rng(17)
+    lens = np.concatenate([[0, 1, 4, 5, 6], rng.integers(0, 400, 300), [0, 0]])
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    tok = rng.integers(0, 50000, int(off[-1])).astype(np.uint32)
+    idx = oracle.OracleIndex(128, 16, 8, 1000, 1e-3, seed=4)
+    want = idx.minhash(off, tok)
+    for threads in [1, 2, 3, 8]:
+        assert np.array_equal(idx.minhash_threads(off, tok, threads), want), threads
+    with pytest.raises(ValueError):
+        idx.minhash_threads(off, tok, 0)
+    idx.close()
+
+
 def _disjoint_pair(rng, n_sh, shared, w=5):
     """Two documents of distinct random tokens whose w-shingle sets share
     exactly `shared` shingles (a common prefix of shared+w-1 tokens)."""
