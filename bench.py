@@ -41,6 +41,12 @@ INT32_VALU_PEAK = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 3.93e13 
 # 1.1747e9 B for a 2.717e8-token batch (65,536 waves).  Valid for the kernel
 # version and grid sizing profiled.
 MINHASH_HBM_BYTES_PER_TOKEN = 1.1747e9 / 2.7175e8
+# Random 8-byte gathers per second into a 57.5 MB buffer that the 256 MB
+# last-level cache holds, measured with torch's index_select
+# (`bench.py --probe-hbm 48`, profiles/hbm_ceilings_probe.md): the rate
+# c2's query-insert probes are compared with, its filters being that size.
+CACHE_RESIDENT_GATHER_PER_S = 5.33e10
+CACHE_BYTES = 256e6
 
 
 def parse():
@@ -239,6 +245,9 @@ def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
         "new_bits_per_batch": new_bits / args.steps,
         "probes_per_s": float(np.mean([probes / (t * 1e-3) for t in qi_ms])),
     }
+    if idx.info()["filter_bytes"] < CACHE_BYTES:
+        qi_roof["cache_resident_gather_per_s"] = CACHE_RESIDENT_GATHER_PER_S
+        qi_roof["probes_frac_of_cache_gather_rate"] = qi_roof["probes_per_s"] / CACHE_RESIDENT_GATHER_PER_S
     if args.wide:
         # the wide kernel does more than the 32-bit operation count per
         # evaluation: its VALU fraction is not reported on that count
@@ -587,6 +596,13 @@ def probe_hbm(torch, gb):
     t_copy = timed(lambda: dst.copy_(src))
     t_gather = timed(lambda: torch.index_select(buf, 0, idx, out=vals))
     t_scatter = timed(lambda: buf.index_copy_(0, idx, vals))
+    # The same random accesses into a buffer the size of the 1M-document
+    # workload's filters (57.5 MB), which the 256 MB last-level cache holds.
+    small_n = 57_510_400 // 8
+    small = torch.zeros(small_n, dtype=torch.int64, device="cuda")
+    sidx = torch.randint(0, small_n, (m,), device="cuda", generator=gen)
+    t_sgather = timed(lambda: torch.index_select(small, 0, sidx, out=vals))
+    t_sscatter = timed(lambda: small.index_copy_(0, sidx, vals))
     return {
         "probe": "hbm ceilings with torch kernels",
         "buffer_GB": gb,
@@ -594,6 +610,9 @@ def probe_hbm(torch, gb):
         "gather_accesses_per_s": m / (t_gather * 1e-3),
         "gather_GBps_at_64B_sectors": m * 64 / (t_gather * 1e-3) / 1e9,
         "scatter_accesses_per_s": m / (t_scatter * 1e-3),
+        "cache_resident_buffer_MB": small_n * 8 / 1e6,
+        "cache_resident_gather_accesses_per_s": m / (t_sgather * 1e-3),
+        "cache_resident_scatter_accesses_per_s": m / (t_sscatter * 1e-3),
         "accesses": m,
     }
 
