@@ -335,11 +335,11 @@ __global__ __launch_bounds__(kBlock, minhash_min_waves(PPL)) void k_minhash(Minh
           for (int p = 0; p < PPL; ++p) mn[p] = min(mn[p], min(c0[p], c1[p]));
           continue;
         }
-        // Common path: the low words of the Mersenne-folded R without the
+        // 32-bit values: the low words of the Mersenne-folded R without the
         // canonical correction, and one flag word per evaluation whose
-        // maximum is tested once.  A flag at or above kPermFlag (about 2^-28
-        // per evaluation, a superset of R >= p) sends the wave through the
-        // exact form for all its evaluations.
+        // maximum is tested once per two shingles.  A flag at or above
+        // kPermFlag (about 2^-28 per evaluation, a superset of R >= p) sends
+        // the wave through the exact form for these evaluations.
         uint32_t v0[PPL], v1[PPL];
         uint32_t fmax = 0;
 #pragma unroll
