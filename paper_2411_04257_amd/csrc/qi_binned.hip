@@ -307,12 +307,16 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
     h[b] = 0;
   }
   sync_lds();
+  // The first sub-tile's records stay in registers from the counting pass to
+  // the splitting pass, so that a bucket of at most kSub2 records is read once.
+  uint64_t rec[kPer2];
   {
     uint64_t g[kPer2];
 #pragma unroll
     for (uint32_t u = 0; u < kPer2; ++u) {
       const uint32_t r = s0 + u * kT2 + threadIdx.x;
       g[u] = r < s1 ? A.rec1[r] : ~0ull;
+      rec[u] = g[u];
     }
     for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
       uint32_t bi[kPer2];
@@ -340,12 +344,6 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
   sync_lds();
   // The next sub-tile's records are loaded as soon as the current ones sit in
   // LDS, so that their latency overlaps the write-out and the barriers.
-  uint64_t rec[kPer2];
-#pragma unroll
-  for (uint32_t u = 0; u < kPer2; ++u) {
-    const uint32_t r = s0 + u * kT2 + threadIdx.x;
-    rec[u] = r < s1 ? A.rec1[r] : ~0ull;
-  }
   for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
     uint32_t rk[kPer2];
 #pragma unroll
