@@ -850,8 +850,6 @@ BinnedGeometry binned_geometry(uint64_t n_docs, uint32_t bands, uint32_t k, uint
   while (s < 24 && (double)(1ull << s) * 1.4142135623730951 <= want) ++s;
   G.bin_bits = s;
   G.bins_per_band = (m_bits + (1ull << s) - 1) >> s;
-  // split the bins of a band evenly between the two passes (pass 2 takes the
-  // odd bit), at most 1024 buckets and 1024 bins per bucket
   // at most 2^20 bins per band (1024 x 1024 over the two passes): wider bins
   // beyond that (only for chunks of more than ~1.9e8 probes per band)
   while (s < 39 && ceil_log2(G.bins_per_band) > 20) {
@@ -859,8 +857,14 @@ BinnedGeometry binned_geometry(uint64_t n_docs, uint32_t bands, uint32_t k, uint
     G.bin_bits = s;
     G.bins_per_band = (m_bits + (1ull << s) - 1) >> s;
   }
+  // split the bins of a band between the two passes, pass 1 taking one bit
+  // more than half (at most 1024 buckets and 1024 bins per bucket): smaller
+  // pass-2 buckets are re-read less between counting and splitting, which
+  // outweighs pass 1's shorter runs (1M-document chunks over 2^17 bins per
+  // band: 18.8 ms per chunk against 19.8 with an even split)
   const uint32_t t = ceil_log2(G.bins_per_band);
-  uint32_t f1 = t / 2;
+  uint32_t f1 = t / 2 + 1;
+  if (f1 > t) f1 = t;
   if (f1 > 10) f1 = 10;
   if (t > 10 && t - 10 > f1) f1 = t - 10;
   G.bucket_bits = s + (t - f1);
