@@ -860,8 +860,8 @@ BinnedGeometry binned_geometry(uint64_t n_docs, uint32_t bands, uint32_t k, uint
   // split the bins of a band between the two passes, pass 1 taking one bit
   // more than half (at most 1024 buckets and 1024 bins per bucket): smaller
   // pass-2 buckets are re-read less between counting and splitting, which
-  // outweighs pass 1's shorter runs (1M-document chunks over 2^17 bins per
-  // band: 18.8 ms per chunk against 19.8 with an even split)
+  // outweighs pass 1's shorter runs (1M-document chunks over 117,006 bins
+  // per band: 18.8 ms per chunk against 19.8 with an even split)
   const uint32_t t = ceil_log2(G.bins_per_band);
   uint32_t f1 = t / 2 + 1;
   if (f1 > t) f1 = t;
