@@ -149,6 +149,39 @@ def test_minhash_independent_of_grid(gpu):
         np.testing.assert_array_equal(out, want)
 
 
+@pytest.mark.parametrize("w", [1, 2, 3, 5, 13])
+def test_minhash_tile_paths_at_document_boundaries(gpu, w):
+    """Documents whose lengths sit on either side of the thresholds of the
+    kernel's tile paths: a tile of 64 positions lies inside one document when
+    that document's end covers the last lane's shingle (63 + max(w, 2)
+    tokens past the tile start), and a full tile (64 shingles of one
+    document) broadcasts its hashes through LDS.  Several grid sizes move the
+    tile starts; every permutation-count instance (1, 2, 4 and 8 per lane)
+    and the wide values are compared with the oracle bit for bit."""
+    rng = np.random.default_rng(100 + w)
+    lens = [0, max(w - 1, 0), w, 62 + w, 63 + w, 64 + w, 65 + w, 126 + w, 127 + w, 128 + w, 129 + w, 0, 3000, 1]
+    lens += rng.integers(60, 200, 12).tolist() + [4000]
+    docs = [rng.integers(0, 50000, int(L)).tolist() for L in lens]
+    off, tok = _csr(docs)
+    doff, dtok = _to_gpu(off, tok)
+    for P in [64, 128, 256, 512]:
+        o = oracle.OracleIndex(P, 8, 8, 1000, 1e-4, 11, w)
+        want = o.minhash(off, tok)
+        want61 = o.minhash61(off, tok) if P == 128 else None
+        for waves in ["4", "12", "64", ""]:
+            print(f"tile paths w={w} P={P} waves={waves or 'auto'}", flush=True)
+            if waves:
+                os.environ["LSHBLOOM_MINHASH_WAVES"] = waves
+            else:
+                os.environ.pop("LSHBLOOM_MINHASH_WAVES", None)
+            g = gpu.LSHBloom(P, 8, 8, 1000, 1e-4, 11, shingle_width=w)
+            np.testing.assert_array_equal(_u32(g.minhash(doff, dtok)), want)
+            if want61 is not None:
+                np.testing.assert_array_equal(g.minhash61(doff, dtok).cpu().numpy().view(np.uint64), want61)
+            g.close()
+    os.environ.pop("LSHBLOOM_MINHASH_WAVES", None)
+
+
 def _random_sigs(rng, n, P):
     return rng.integers(0, 2**32, (n, P), dtype=np.uint64).astype(np.uint32)
 
