@@ -796,29 +796,52 @@ __global__ __launch_bounds__(256) void k_bq_resolve(BinnedLaunch A, uint32_t sli
     const uint64_t key = A.keys[(int64_t)j * A.n + i];
     const uint64_t h1 = fmix64(key ^ A.salt1), h2 = fmix64(key ^ A.salt2) | 1ull;
     bool hit = true;
-    for (uint32_t l = 1; l < A.k && hit; ++l) {
-      const uint64_t g = umulhi64(h1 + (uint64_t)l * h2, A.m_bits);
-      const uint64_t lbin = g >> G.bin_bits;
-      const uint64_t d = A.dir[(uint64_t)j * G.bins_per_band + lbin];
-      const uint32_t pcap = (uint32_t)d;
-      const uint64_t *T = A.rec1 + 2ull * (d >> 32);
-      const uint32_t lb = (uint32_t)(g - (lbin << G.bin_bits));
-      bool found = false;
-      uint32_t v = 0;
-      uint32_t h = pcap ? slot_of(lb, pcap) : 0;
-      for (uint32_t tries = 0; tries < pcap; ++tries) {
-        const uint64_t e = T[h];
-        const uint32_t ek = (uint32_t)(e >> 32);
-        if (ek == lb + 1) {
-          v = (uint32_t)e;
-          found = true;
-          break;
+    // Probes 1..k-1 in groups of four: the four directory entries and the
+    // four first table slots are loaded before any is examined, so that a
+    // band whose probes all hit waits for k/4 rounds of dependent loads, not
+    // k.  The answer is the same conjunction; the extra reads of a group
+    // after a miss are reads of valid tables.
+    for (uint32_t l0 = 1; l0 < A.k && hit; l0 += 4) {
+      const uint32_t nl = min(4u, A.k - l0);
+      uint32_t lb[4], pcap[4], h[4];
+      const uint64_t *T[4];
+      uint64_t e[4];
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        pcap[u] = 0;
+        if (u < nl) {
+          const uint64_t g = umulhi64(h1 + (uint64_t)(l0 + u) * h2, A.m_bits);
+          const uint64_t lbin = g >> G.bin_bits;
+          const uint64_t d = A.dir[(uint64_t)j * G.bins_per_band + lbin];
+          pcap[u] = (uint32_t)d;
+          T[u] = A.rec1 + 2ull * (d >> 32);
+          lb[u] = (uint32_t)(g - (lbin << G.bin_bits));
         }
-        if (ek == 0) break;
-        h = (h + 1 == pcap) ? 0 : h + 1;
       }
-      // not published: the only document probing the bit is this one
-      hit = found && (v == kInit || v < (uint32_t)i);
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        h[u] = pcap[u] ? slot_of(lb[u], pcap[u]) : 0;
+        e[u] = pcap[u] ? T[u][h[u]] : 0;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < 4; ++u) {
+        if (u >= nl || !hit) break;
+        bool found = false;
+        uint32_t v = 0;
+        for (uint32_t tries = 0; tries < pcap[u]; ++tries) {
+          const uint32_t ek = (uint32_t)(e[u] >> 32);
+          if (ek == lb[u] + 1) {
+            v = (uint32_t)e[u];
+            found = true;
+            break;
+          }
+          if (ek == 0) break;
+          h[u] = (h[u] + 1 == pcap[u]) ? 0 : h[u] + 1;
+          e[u] = T[u][h[u]];
+        }
+        // not published: the only document probing the bit is this one
+        hit = found && (v == kInit || v < (uint32_t)i);
+      }
     }
     if (hit) flag = 1;
   }
