@@ -12,6 +12,7 @@ signature is, at a filter fill where the Bloom false-positive rate is ~1e-80.
 """
 
 import ctypes
+import math
 
 import numpy as np
 import pytest
@@ -113,4 +114,32 @@ def test_c4_full_filters_repeats_and_inserted_bits(gpu):
         sig = synth.signature_batch(int(i), 1, wl.num_perm, wl.bands, wl.rows, B, ex["repeat_frac"],
                                     ex["in_batch_frac"], wl.corpus_seed).numpy().view(np.uint32)[0]
         _assert_bits_set(gpu, g, sig, wl.bands, wl.rows, salts, m, k)
+    g.close()
+
+
+def test_p_eff_composition_through_the_binned_path(gpu):
+    """Unique random signatures streamed through the benchmark's launch
+    configuration (65,536-signature chunks, binned query-insert) at a fill
+    where false positives are common: the flagged count follows
+    sum_i 1-(1-FP_i)^b with FP_i the Bloom rate after i inserts (Section 4.3)
+    within a Poisson interval, and the first chunk's flags equal the
+    oracle's.  Every flag here comes from bits set by other documents, before
+    or inside the chunk, so the resolve step's table lookups decide it."""
+    n, P, bands, rows, B = 400_000, 64, 8, 8, 65_536
+    g = gpu.LSHBloom(P, bands, rows, 200_000, 5e-2, 23, chunk_docs=B)
+    sigs = synth.signature_batch(0, n, P, bands, rows, B, 0.0, 0.0, 77, device="cuda")
+    flags = torch.cat([g.query_insert(sigs[a:a + B]).cpu() for a in range(0, n, B)]).numpy()
+    assert g.info()["device_status"] == 0
+    m, k = g.m_bits, g.k
+    i = np.arange(n)
+    f = (1 - np.exp(-k * i / m)) ** k
+    want = float(np.sum(1 - (1 - f) ** bands))
+    got = int(flags.sum())
+    print(f"p_eff composition: flagged {got}, expected {want:.0f}", flush=True)
+    assert want > 10_000
+    assert abs(got - want) < 4.5 * math.sqrt(want) + 2, (got, want)
+    o = oracle.OracleIndex(P, bands, rows, 200_000, 5e-2, 23)
+    head = sigs[:B].cpu().numpy().view(np.uint32)
+    assert flags[:B].tolist() == o.query_insert(head).tolist()
+    o.close()
     g.close()
