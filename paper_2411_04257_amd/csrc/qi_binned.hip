@@ -120,25 +120,44 @@ __global__ __launch_bounds__(256) void k_bq_keys(BinnedLaunch A) {
   const int64_t d0 = (int64_t)blockIdx.x * td;
   const uint32_t nd = (uint32_t)min((int64_t)td, A.n - d0);
   const uint32_t nq = nd * br;
+  // Element q = d * br + c of the tile, walked in steps of kThreads: (d, c)
+  // advance by (kThreads / br, kThreads % br) with one carry, instead of a
+  // division per element.
+  const uint32_t dstep = kThreads / br, cstep = kThreads - dstep * br;
+  uint32_t d = threadIdx.x / br, c = threadIdx.x - d * br;
   for (uint32_t q0 = 0; q0 < nq; q0 += 8 * kThreads) {
-    uint32_t v[8];
+    uint32_t v[8], dd[8], cc[8];
 #pragma unroll
     for (uint32_t u = 0; u < 8; ++u) {
       const uint32_t q = q0 + u * kThreads + threadIdx.x;
-      const uint32_t d = q / br, c = q - d * br;
+      dd[u] = d;
+      cc[u] = c;
       v[u] = q < nq ? A.sigs[(d0 + d) * (int64_t)A.num_perm + c] : 0u;
+      d += dstep;
+      c += cstep;
+      if (c >= br) {
+        c -= br;
+        ++d;
+      }
     }
 #pragma unroll
     for (uint32_t u = 0; u < 8; ++u) {
       const uint32_t q = q0 + u * kThreads + threadIdx.x;
-      const uint32_t d = q / br, c = q - d * br;
-      if (q < nq) srow[d * stride + c] = v[u];
+      if (q < nq) srow[dd[u] * stride + cc[u]] = v[u];
     }
   }
   __syncthreads();
+  // Key p = j * nd + dk: (j, dk) advance the same way.
+  const uint32_t jstep = kThreads / nd, kstep = kThreads - jstep * nd;
+  uint32_t j = threadIdx.x / nd, dk = threadIdx.x - j * nd;
   for (uint32_t p = threadIdx.x; p < nd * A.bands; p += kThreads) {
-    const uint32_t j = p / nd, d = p - j * nd;
-    A.keys[(int64_t)j * A.n + d0 + d] = band_key(&srow[d * stride + j * A.rows], A.rows, A.salt_m);
+    A.keys[(int64_t)j * A.n + d0 + dk] = band_key(&srow[dk * stride + j * A.rows], A.rows, A.salt_m);
+    j += jstep;
+    dk += kstep;
+    if (dk >= nd) {
+      dk -= nd;
+      ++j;
+    }
   }
 }
 
