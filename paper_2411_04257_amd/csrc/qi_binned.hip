@@ -186,33 +186,24 @@ constexpr uint32_t kT1 = 1024;
 constexpr uint32_t kPer1 = 16;
 constexpr uint32_t kSub1 = kT1 * kPer1;
 
-__device__ __forceinline__ void tile_hashes(const BinnedLaunch &A, uint32_t j, int64_t d0, uint32_t nd, uint64_t *h1,
-                                            uint64_t *h2) {
-  const uint64_t *K = A.keys + (int64_t)j * A.n + d0;
-  for (uint32_t d = threadIdx.x; d < nd; d += blockDim.x) {
-    const uint64_t key = K[d];
-    h1[d] = fmix64(key ^ A.salt1);
-    h2[d] = fmix64(key ^ A.salt2) | 1ull;
-  }
-}
-
 __global__ __launch_bounds__(256) void k_bq_count1(BinnedLaunch A) {
-  __shared__ uint64_t h1[kTileDocs], h2[kTileDocs];
   extern __shared__ uint32_t hist[];  // [F1]
   const BinnedGeometry &G = A.G;
   const uint32_t F1 = G.buckets_per_band;
   const uint32_t j = blockIdx.y, tile = blockIdx.x;
   const int64_t d0 = (int64_t)tile * kTileDocs;
   const uint32_t nd = (uint32_t)min((int64_t)kTileDocs, A.n - d0);
-  tile_hashes(A, j, d0, nd, h1, h2);
   for (uint32_t f = threadIdx.x; f < F1; f += kThreads) hist[f] = 0;
   sync_lds();
-  const uint32_t total = kTileDocs * A.k;
-  for (uint32_t q = threadIdx.x; q < total; q += kThreads) {
-    const uint32_t d = q & (kTileDocs - 1), l = q >> kTileLog;
-    if (d >= nd) continue;
-    const uint64_t g = umulhi64(h1[d] + (uint64_t)l * h2[d], A.m_bits);
-    atomicAdd(&hist[(uint32_t)(g >> G.bucket_bits)], 1u);
+  // whole documents per thread: the pair of hashes stays in registers
+  const uint64_t *K = A.keys + (int64_t)j * A.n + d0;
+  for (uint32_t d = threadIdx.x; d < nd; d += kThreads) {
+    const uint64_t key = K[d];
+    const uint64_t h1 = fmix64(key ^ A.salt1), h2 = fmix64(key ^ A.salt2) | 1ull;
+    for (uint32_t l = 0; l < A.k; ++l) {
+      const uint64_t g = umulhi64(h1 + (uint64_t)l * h2, A.m_bits);
+      atomicAdd(&hist[(uint32_t)(g >> G.bucket_bits)], 1u);
+    }
   }
   sync_lds();
   const uint64_t row = ((uint64_t)j * F1) * G.n_tiles + tile;  // + f * n_tiles
@@ -225,16 +216,13 @@ __global__ __launch_bounds__(1024) void k_bq_scatter1(BinnedLaunch A) {
   const uint32_t F1 = G.buckets_per_band;
   const uint32_t F1r = (F1 + 3) & ~3u;
   uint64_t *stage = (uint64_t *)smem;              // [kSub1]
-  uint64_t *h1 = stage + kSub1;                    // [kTileDocs]
-  uint64_t *h2 = h1 + kTileDocs;                   // [kTileDocs]
-  uint32_t *hist = (uint32_t *)(h2 + kTileDocs);   // [F1]
+  uint32_t *hist = (uint32_t *)(stage + kSub1);    // [F1]
   uint32_t *lstart = hist + F1r;                   // [F1]
   uint32_t *cur = lstart + F1r;                    // [F1]
   uint32_t *part = cur + F1r;                      // [16]
   const uint32_t j = blockIdx.y, tile = blockIdx.x;
   const int64_t d0 = (int64_t)tile * kTileDocs;
   const uint32_t nd = (uint32_t)min((int64_t)kTileDocs, A.n - d0);
-  tile_hashes(A, j, d0, nd, h1, h2);
   const uint64_t row = ((uint64_t)j * F1) * G.n_tiles + tile;  // + f * n_tiles
   for (uint32_t f = threadIdx.x; f < F1; f += kT1) {
     hist[f] = 0;
@@ -242,16 +230,26 @@ __global__ __launch_bounds__(1024) void k_bq_scatter1(BinnedLaunch A) {
   }
   sync_lds();
   const uint32_t total = kTileDocs * A.k;
+  // slot q = l * kTileDocs + d with kT1 == kTileDocs: thread t always holds
+  // document t, whose pair of hashes stays in registers
+  static_assert(kT1 == kTileDocs, "one document per thread");
+  const uint32_t d = threadIdx.x;
+  uint64_t dh1 = 0, dh2 = 0;
+  if (d < nd) {
+    const uint64_t key = A.keys[(int64_t)j * A.n + d0 + d];
+    dh1 = fmix64(key ^ A.salt1);
+    dh2 = fmix64(key ^ A.salt2) | 1ull;
+  }
   for (uint32_t q0 = 0; q0 < total; q0 += kSub1) {
     uint64_t rec[kPer1];
     uint32_t rk[kPer1];
 #pragma unroll
     for (uint32_t u = 0; u < kPer1; ++u) {
       const uint32_t q = q0 + u * kT1 + threadIdx.x;
-      const uint32_t d = q & (kTileDocs - 1), l = q >> kTileLog;
+      const uint32_t l = q >> kTileLog;
       rec[u] = ~0ull;
       if (q < total && d < nd) {
-        const uint64_t g = umulhi64(h1[d] + (uint64_t)l * h2[d], A.m_bits);
+        const uint64_t g = umulhi64(dh1 + (uint64_t)l * dh2, A.m_bits);
         rk[u] = atomicAdd(&hist[(uint32_t)(g >> G.bucket_bits)], 1u);
         rec[u] = (l == 0 ? kProbe0 : 0ull) | ((uint64_t)(d0 + d) << 40) | g;
       }
@@ -942,7 +940,7 @@ hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bq_scan_buckets, dim3(1), dim3(kThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds1 = kSub1 * 8 + kTileDocs * 16 + 3 * (size_t)((G.buckets_per_band + 3) & ~3u) * 4 + 16 * 4;
+  const size_t lds1 = kSub1 * 8 + 3 * (size_t)((G.buckets_per_band + 3) & ~3u) * 4 + 16 * 4;
   hipLaunchKernelGGL(k_bq_scatter1, dim3(G.n_tiles, a.bands), dim3(kT1), lds1, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t lds2 = kSub2 * 8 + 3 * (size_t)G.bins_per_bucket * 4 + 16 * 4;
