@@ -158,6 +158,23 @@ int lshbloom_minhash(lshbloom_t *h, const int64_t *d_offsets, const uint32_t *d_
 int lshbloom_query_insert(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags,
                           lshbloom_stream_t stream);
 
+/* Allocation-free lshbloom_query_insert, for callers that cannot allocate
+ * device memory while they run (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, result, ordering
+ * and errors as lshbloom_query_insert; it runs the direct (first-setter
+ * table) algorithm with its table and per-pair arrays in a fixed
+ * device array of the library (33 MiB per GPU, held until the process ends),
+ * not in the handle's workspace, and calls no allocating routine.  At most
+ * LSHBLOOM_NOALLOC_MAX_DOCS documents per call (LSHBLOOM_EINVAL beyond);
+ * larger calls are processed in chunks that fit the array.  Every call of
+ * this function on one GPU uses the same array: calls of it that overlap
+ * on one GPU (two handles driven from different streams without ordering
+ * between them) race and give wrong flags; calls on one handle are ordered
+ * by the handle. */
+#define LSHBLOOM_NOALLOC_MAX_DOCS 65536u
+int lshbloom_query_insert_noalloc(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags,
+                                  lshbloom_stream_t stream);
+
 /* Query only (Section 4.2): flags against the filters as they are; nothing is
  * inserted and documents of the batch do not see each other. */
 int lshbloom_query(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags,

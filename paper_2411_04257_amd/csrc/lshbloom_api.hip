@@ -60,6 +60,41 @@ uint64_t next_pow2(uint64_t v) {
   return p;
 }
 
+// Scratch of lshbloom_query_insert_noalloc: the direct algorithm's
+// first-setter table (kNaTableSlots 8-byte slots), then the band keys (8 B),
+// found-bit masks (8 B) and hit bytes (1 B) of up to kNaPairs (document,
+// band) pairs of one chunk.  One copy per device, in the code object; its
+// device address is looked up once per device (na_scratch_ptr) and only that
+// address is handed to kernels.
+constexpr uint64_t kNaTableSlots = 1ull << 21;  // 16 MiB
+constexpr uint64_t kNaPairs = 1ull << 20;       // 17 MiB of keys, masks and hit bytes
+constexpr uint64_t kNaBytes = kNaTableSlots * 8 + kNaPairs * (8 + 8) + kNaPairs;
+constexpr int kNaMaxDevices = 64;
+
+__device__ __align__(256) uint8_t scratch[kNaBytes];
+
+std::mutex g_na_mu;
+void *g_na_ptr[kNaMaxDevices] = {};
+bool g_na_done[kNaMaxDevices] = {};
+hipError_t g_na_err[kNaMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked up
+// on the first call for that device.
+hipError_t na_scratch_ptr(int device, void **out) {
+  *out = nullptr;
+  if (device < 0 || device >= kNaMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (!g_na_done[device]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    g_na_err[device] = e;
+    g_na_ptr[device] = e == hipSuccess ? p : nullptr;
+    g_na_done[device] = true;
+  }
+  *out = g_na_ptr[device];
+  return g_na_err[device];
+}
+
 }  // namespace
 
 
@@ -419,6 +454,12 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
     delete h;
     return nullptr;
   }
+  // The allocation-free query-insert's scratch address on this device (its
+  // failure is reported by that call only).
+  {
+    void *na = nullptr;
+    (void)na_scratch_ptr(h->device, &na);
+  }
   // Persistent MinHash grid: sized per call (minhash_waves_for_docs) unless
   // fixed by the environment.
   h->cus = dp.multiProcessorCount;
@@ -539,6 +580,59 @@ int lshbloom_query_insert(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs,
   if (rc) return rc;
   e = end_ordered(h, s);
   if (e != hipSuccess) return fail_hip(h, e, "query_insert: event");
+  h->docs_inserted += (uint64_t)n_docs;
+  return LSHBLOOM_OK;
+}
+
+int lshbloom_query_insert_noalloc(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags,
+                                  lshbloom_stream_t stream) {
+  if (!h) return check_ready(h);
+  std::lock_guard<std::mutex> lk(h->mu);
+  int rc = check_ready(h);
+  if (rc) return rc;
+  if (n_docs < 0 || (n_docs > 0 && (!d_sigs || !d_flags))) {
+    set_err("query_insert_noalloc: need n_docs >= 0 and non-null sigs and flags");
+    return LSHBLOOM_EINVAL;
+  }
+  if ((uint64_t)n_docs > LSHBLOOM_NOALLOC_MAX_DOCS) {
+    set_err("query_insert_noalloc: %lld documents exceed the limit of %llu per call", (long long)n_docs,
+            (unsigned long long)LSHBLOOM_NOALLOC_MAX_DOCS);
+    return LSHBLOOM_EINVAL;
+  }
+  if (n_docs == 0) return LSHBLOOM_OK;
+  void *na = nullptr;
+  hipError_t e = na_scratch_ptr(h->device, &na);
+  if (e != hipSuccess || !na) return fail_hip(nullptr, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                              "query_insert_noalloc: scratch address");
+  // Chunk so that the table holds at least twice the chunk's probes and the
+  // pair arrays its (document, band) pairs.
+  const uint64_t pd = (uint64_t)h->prm.bands * h->k;
+  uint64_t chunk = std::min<uint64_t>(kNaTableSlots / (2 * pd), kNaPairs / h->prm.bands);
+  chunk = std::min<uint64_t>(chunk, lb::kMaxChunkDocs);
+  if (chunk < 1) {
+    set_err("query_insert_noalloc: %llu probes per document exceed the scratch", (unsigned long long)pd);
+    return LSHBLOOM_EINVAL;
+  }
+  if (forced_fault(h)) return LSHBLOOM_EHIP;
+  hipStream_t s = (hipStream_t)stream;
+  e = begin_ordered(h, s);
+  if (e != hipSuccess) return fail_hip(h, e, "query_insert_noalloc: stream wait");
+  uint8_t *base = static_cast<uint8_t *>(na);
+  for (int64_t c0 = 0; c0 < n_docs; c0 += (int64_t)chunk) {
+    const int64_t cn = std::min<int64_t>((int64_t)chunk, n_docs - c0);
+    lb::BloomLaunch a = bloom_args(h, d_sigs + c0 * (int64_t)h->prm.num_perm, cn);
+    const uint64_t slots = std::min<uint64_t>(kNaTableSlots, next_pow2(std::max<uint64_t>(1024, 2 * cn * pd)));
+    a.table = reinterpret_cast<uint64_t *>(base);
+    a.table_mask = slots - 1;
+    a.keys = reinterpret_cast<uint64_t *>(base + kNaTableSlots * 8);
+    a.masks = reinterpret_cast<uint64_t *>(base + kNaTableSlots * 8 + kNaPairs * 8);
+    a.hitb = base + kNaTableSlots * 8 + kNaPairs * 16;
+    a.flags = d_flags + c0;
+    e = lb::launch_query_insert_chunk(a, slots, s);
+    if (e != hipSuccess) return fail_hip(h, e, "query_insert_noalloc: launch");
+  }
+  e = end_ordered(h, s);
+  if (e != hipSuccess) return fail_hip(h, e, "query_insert_noalloc: event");
   h->docs_inserted += (uint64_t)n_docs;
   return LSHBLOOM_OK;
 }

@@ -102,7 +102,9 @@ EXPORTS = [
     "lshbloom_pipeline_info", "lshbloom_pipeline_destroy",
     "lshbloom_exact_create", "lshbloom_exact_destroy", "lshbloom_exact_query_insert", "lshbloom_exact_stats",
     "lshbloom_query_insert_keys", "lshbloom_minhash61", "lshbloom_band_keys61",
+    "lshbloom_query_insert_noalloc",
 ]
+NOALLOC_MAX_DOCS = 65536
 
 _lib = None
 
@@ -124,6 +126,7 @@ def load(path: str = LIB_PATH):
     L.lshbloom_destroy.restype = None
     L.lshbloom_minhash.argtypes = [vp, vp, vp, i64, vp, vp]
     L.lshbloom_query_insert.argtypes = [vp, vp, i64, vp, vp]
+    L.lshbloom_query_insert_noalloc.argtypes = [vp, vp, i64, vp, vp]
     L.lshbloom_query.argtypes = [vp, vp, i64, vp, vp]
     L.lshbloom_insert.argtypes = [vp, vp, i64, vp]
     L.lshbloom_band_keys.argtypes = [vp, vp, i64, vp, vp]
@@ -165,7 +168,8 @@ def load(path: str = LIB_PATH):
     L.lshbloom_exact_stats.restype = ctypes.c_int
     L.lshbloom_last_error.argtypes = []
     L.lshbloom_last_error.restype = ctypes.c_char_p
-    for name in ("lshbloom_minhash", "lshbloom_query_insert", "lshbloom_query", "lshbloom_insert",
+    for name in ("lshbloom_minhash", "lshbloom_query_insert", "lshbloom_query_insert_noalloc", "lshbloom_query",
+                 "lshbloom_insert",
                  "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters",
                  "lshbloom_count_set_bits", "lshbloom_save", "lshbloom_load", "lshbloom_info", "lshbloom_optimal_bands"):
         getattr(L, name).restype = ctypes.c_int
@@ -265,6 +269,15 @@ class LSHBloom:
         if n:
             _check(load().lshbloom_query_insert(self._h, _dev_ptr(sigs, _U32, "sigs"), n,
                                                 _dev_ptr(out, (torch.uint8,), "out"), _stream()))
+        return out
+
+    def query_insert_noalloc(self, sigs: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+        """query_insert through the allocation-free entry point (out must be given)."""
+        n = self._rows_of(sigs)
+        if out.numel() != n:
+            raise ValueError("out must hold one flag per document")
+        _check(load().lshbloom_query_insert_noalloc(self._h, _dev_ptr(sigs, _U32, "sigs") if n else None, n,
+                                                    _dev_ptr(out, (torch.uint8,), "out") if n else None, _stream()))
         return out
 
     def query(self, sigs: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
