@@ -1,25 +1,32 @@
 #!/usr/bin/env python3
 """End-to-end LSHBloom throughput on one MI355X.
 
-A step is one pass of the whole hot path over one batch of documents already
-resident in HBM: MinHash signatures of the batch, then the in-order
-query-insert against the per-band Bloom filters (which keep growing across
-steps, as in a real stream).  The default workload is the plain method on
-GPU: a 1M-document synthetic corpus (Zipf(1.1) tokens over a 50k vocabulary,
-lognormal lengths with median 3,000 and sigma 0.8 capped at 50,000, 20%
-near-duplicates with Jaccard 0.6-0.95), num_perm = 128, 16 bands x 8 rows,
-filters sized for n = 1M at a per-band fp rate of 1e-6, batches of 65,536.
+A step is one pass of the whole hot path over one batch of 1M documents:
+MinHash signatures of the batch, then the in-order query-insert against the
+per-band Bloom filters (which keep growing across steps, as in a real
+stream).  The default workload is the batched form on the 10M-document
+configuration: synthetic documents (Zipf(1.1) tokens over a 50k vocabulary,
+Pareto(1.5, min 20) lengths capped at 200,000, 25% near-duplicates), 5-token
+shingles, num_perm = 256, 32 bands x 8 rows, filters sized for n = 1e8 at a
+per-band fp rate of 1e-8 (15.3 GB), batches of 1M documents handed over as
+host CSR arrays and flags returned to host memory (the pipeline overlaps the
+copies, length-bucketed MinHash and the query-insert).  Beside it the same
+host batches go through plain per-batch calls, and the same batches through
+plain calls on inputs already in HBM.
 
-Prints one JSON line (rank 0) with docs/s, the MinHash kernel's ALU roofline
-and the CPU oracle timed on a bounded prefix of the same stream.
+Prints one JSON line with docs/s, the dominant stage's roofline (the
+query-insert, timed with HIP events on the stream it runs on) and the CPU
+oracle timed on a bounded prefix of the same stream.
 """
 
 from __future__ import annotations
 
 import argparse
 import dataclasses
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -27,26 +34,59 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Per-unit VALU lane-operation counts of the MinHash hot loops (gfx950 ISA of
-# k_minhash<PPL=2, w=5>): one SHA-1 shingle hash of a 5-token shingle (573),
-# and one exact (a*x+b) mod (2^61-1) evaluation in a full 64-shingle tile with
-# its share of the running min and of the flag test (3 v_mad_u64_u32 + 1 add,
-# 1/2 of a v_min3 and 1/2 of a v_max3, each folding two evaluations: 80
-# instructions per 16 evaluations).
-OPS_PER_SHINGLE_HASH = 573
-OPS_PER_SHINGLE_PERM = 5.0
+CSRC = os.path.join(ROOT, "paper_2411_04257_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
 INT32_VALU_PEAK = 256 * 4 * 16 * 2.4e9  # CUs x SIMDs x lanes x clock = 3.93e13 lane-ops/s
-# HBM bytes per token that k_minhash moved, from rocprofv3 FETCH_SIZE (x2.0) and
-# WRITE_SIZE (x1.0) scaled by a 1 GiB copy (profiles/k_minhash_c2_counters.md):
-# 1.1747e9 B for a 2.717e8-token batch (65,536 waves).  Valid for the kernel
-# version and grid sizing profiled.
-MINHASH_HBM_BYTES_PER_TOKEN = 1.1747e9 / 2.7175e8
-# Random 8-byte gathers per second into a 57.5 MB buffer that the 256 MB
-# last-level cache holds, measured with torch's index_select
-# (`bench.py --probe-hbm 48`, profiles/hbm_ceilings_probe.md): the rate
-# c2's query-insert probes are compared with, its filters being that size.
-CACHE_RESIDENT_GATHER_PER_S = 5.33e10
+HBM_PEAK = 8e12
 CACHE_BYTES = 256e6
+
+
+def source_tag(*files) -> str:
+    """First 16 hex digits of the SHA-256 of the named kernel sources: the
+    version of the kernels a counter profile was taken of."""
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profile_rows(name: str, tag: str) -> dict:
+    """Rows `| key | tag | v1 | v2 | ... |` of profiles/<name> whose tag is
+    `tag` (key -> list of floats); rows of other kernel versions are ignored."""
+    path = os.path.join(PROFILES, name)
+    out = {}
+    if not os.path.exists(path):
+        return out
+    pat = re.compile(r"^\|\s*(\S+)\s*\|\s*([0-9a-f]{16})\s*\|((?:\s*[-+0-9.eE]+\s*\|)+)\s*$")
+    with open(path) as fh:
+        for line in fh:
+            m = pat.match(line.strip())
+            if m and m.group(2) == tag:
+                out[m.group(1)] = [float(v) for v in m.group(3).split("|") if v.strip()]
+    return out
+
+
+def qi_traffic(workload: str):
+    """HBM bytes per batch of the query-insert kernels from the counter runs
+    in profiles/query_insert_counters.md (FETCH_SIZE and WRITE_SIZE, scaled by
+    a plain copy), for the kernel version built here; None otherwise."""
+    rows = profile_rows("query_insert_counters.md", source_tag("qi_binned.hip", "qi_binned.h", "device_math.h"))
+    r = rows.get(workload)
+    return None if r is None else r[0] + r[1]
+
+
+def minhash_counts(ppl: int, w: int):
+    """VALU lane-operations per shingle hash and per evaluation of the
+    k_minhash<PPL, w> instance, from its SQ_INSTS_VALU counter runs in
+    profiles/k_minhash_valu_counters.md for the kernel version built here."""
+    rows = profile_rows("k_minhash_valu_counters.md", source_tag("kernels.hip", "device_math.h"))
+    return rows.get(f"ppl{ppl}_w{w}")
+
+
+def minhash_ppl(num_perm: int) -> int:
+    """Permutations per lane of the k_minhash instance launched for num_perm."""
+    return (num_perm + 63) // 64
 
 
 def parse():
@@ -54,23 +94,29 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5"])
-    ap.add_argument("--loads", default="2000,10000,50000,250000,1000000,2000000",
+    ap.add_argument("--workload", default="c3", choices=["c2", "c3", "c4", "c5"])
+    ap.add_argument("--loads", default="1000,2000,10000,50000,250000,1000000,2000000",
                     help="c5: offered loads in docs/s")
+    ap.add_argument("--requests", type=int, default=1000, help="c5: requests per offered load")
     ap.add_argument("--preload", type=int, default=None, help="c5: documents inserted before serving")
-    ap.add_argument("--cpu-sample-docs", type=int, default=3072)
+    ap.add_argument("--cpu-sample-docs", type=int, default=None,
+                    help="documents the single-thread oracle is timed on (default: the workload's)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--qi-mode", type=int, default=0, help="0 automatic, 1 direct, 2 binned query-insert")
-    ap.add_argument("--form", default="plain", choices=["plain", "batched", "fidelity"],
-                    help="plain: per-batch calls on HBM-resident inputs; batched: the host-to-host pipeline "
-                         "(length buckets, overlapping slots, hipGraph, autotuner) compared with per-batch "
-                         "calls that copy the same host batches; fidelity: LSHBloom against the exact "
+    ap.add_argument("--form", default=None, choices=["plain", "batched", "fidelity"],
+                    help="batched (default for c3): host CSR in, host flags out through the pipeline "
+                         "(length buckets, overlapping slots, hipGraph, autotuner), beside plain per-batch calls "
+                         "fed the same host batches and plain calls on inputs already in HBM; plain (default "
+                         "for c2): per-batch calls on HBM-resident inputs; fidelity: LSHBloom against the exact "
                          "MinHashLSH band index on the same signatures, scored on the corpus's near-dup labels")
+    ap.add_argument("--full-stream", action="store_true",
+                    help="c4: run the whole 1e9-signature stream (1,000 batches) and check the flagged fraction "
+                         "of unique signatures against the p_eff composition law")
     ap.add_argument("--wide", action="store_true",
                     help="plain form: the wide-value variant (61-bit MinHash values, their band keys, "
                          "query-insert from keys) in each step")
     ap.add_argument("--batch", type=int, default=None,
-                    help="documents per batch (default: the workload's; c3 leaves it open)")
+                    help="documents per batch (default: the workload's)")
     ap.add_argument("--chunk-docs", type=int, default=None,
                     help="documents per in-order query-insert chunk (default: the batch)")
     ap.add_argument("--copy-bytes", type=int, default=0,
@@ -80,11 +126,15 @@ def parse():
                     help="instead of a workload: measure the memory system's ceilings with torch's own kernels "
                          "(streaming copy, random 8-byte gather and scatter over a GB-sized buffer) and exit")
     a = ap.parse_args()
-    default_steps = {"c2": (13, 2), "c3": (9, 1), "c4": (20, 2), "c5": (0, 0)}[a.workload]
+    if a.form is None:
+        a.form = "batched" if a.workload == "c3" else "plain"
+    default_steps = {"c2": (13, 2), "c3": (20, 5), "c4": (20, 2), "c5": (0, 0)}[a.workload]
     if a.steps is None:
         a.steps = default_steps[0]
     if a.warmup is None:
         a.warmup = default_steps[1]
+    if a.cpu_sample_docs is None:
+        a.cpu_sample_docs = {"c2": 3072, "c3": 20000}.get(a.workload, 3072)
     return a
 
 
@@ -94,15 +144,16 @@ def shingle_count(lengths, w=5):
     return int(np.where(lengths >= w, lengths - w + 1, np.minimum(lengths, 1)).sum())
 
 
-def cpu_baseline(wl, corpus, n_docs):
+def cpu_baseline(wl, h_off, h_tok, n_docs):
     """The oracle, single-threaded, over the first n_docs documents of the
-    same stream (MinHash + in-order query-insert with full-size filters)."""
+    same stream (MinHash + in-order query-insert with full-size filters), and
+    the same oracle with its MinHash over the host's cores on 8x as many."""
     import numpy as np
 
     import oracle
 
-    off = corpus.offsets[: n_docs + 1].cpu().numpy()
-    tok = corpus.tokens[: int(off[-1])].cpu().numpy().view(np.uint32)
+    off = np.ascontiguousarray(h_off[: n_docs + 1])
+    tok = h_tok[: int(off[-1])].view(np.uint32)
     o = oracle.OracleIndex(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
     t0 = time.perf_counter()
     sigs = o.minhash(off, tok)
@@ -111,7 +162,7 @@ def cpu_baseline(wl, corpus, n_docs):
     o.close()
     out = {"value": n_docs / dt, "unit": "docs/s", "cores": 1, "kind": "oracle",
            "sample": f"first {n_docs} documents of the same stream ({int(off[-1])} tokens), "
-                     f"MinHash + in-order query-insert, single thread, {dt:.1f} s"}
+                     f"MinHash + in-order query-insert against full-size filters, single thread, {dt:.1f} s"}
 
     # The same oracle with MinHash shared out over the host's cores (each
     # document still the sequential per-document definition) and the
@@ -119,9 +170,9 @@ def cpu_baseline(wl, corpus, n_docs):
     threads = len(os.sched_getaffinity(0))
     if os.environ.get("OMP_NUM_THREADS", "").isdigit():
         threads = min(threads, int(os.environ["OMP_NUM_THREADS"]))
-    n_par = min(corpus.n_docs, 8 * n_docs)
-    off = corpus.offsets[: n_par + 1].cpu().numpy()
-    tok = corpus.tokens[: int(off[-1])].cpu().numpy().view(np.uint32)
+    n_par = min(len(h_off) - 1, 8 * n_docs)
+    off = np.ascontiguousarray(h_off[: n_par + 1])
+    tok = h_tok[: int(off[-1])].view(np.uint32)
     o = oracle.OracleIndex(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
     t0 = time.perf_counter()
     sigs = o.minhash_threads(off, tok, threads)
@@ -145,6 +196,57 @@ def qi_algorithmic_bytes(steps, batch, probes, new_bits, num_perm):
     return SECTOR * (steps * probes + new_bits) + steps * batch * (4 * num_perm + 1)
 
 
+def qi_roofline(wl, args, batch, probes, new_bits, qi_ms, filter_bytes, traffic_key):
+    """Roofline object of the query-insert stage: algorithmic bytes per batch
+    over the mean stage time measured with HIP events on its stream."""
+    import numpy as np
+
+    steps = len(qi_ms)
+    per_batch = qi_algorithmic_bytes(steps, batch, probes, new_bits, wl.num_perm) / steps
+    ach = per_batch / (float(np.mean(qi_ms)) * 1e-3)
+    traffic = qi_traffic(traffic_key) if traffic_key else None
+    roof = {
+        "bound": "hbm",
+        "kernel": "query-insert (all kernels of a batch's in-order test-and-set)",
+        "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": ach / HBM_PEAK,
+        "traffic": traffic,
+        "algorithmic_bytes_per_batch": per_batch,
+        "new_bits_per_batch": new_bits / steps,
+        "probes_per_batch": probes,
+        "stage_ms_mean": float(np.mean(qi_ms)),
+        "probes_per_s": probes / (float(np.mean(qi_ms)) * 1e-3),
+    }
+    if traffic:
+        roof["traffic_GBps"] = traffic / (float(np.mean(qi_ms)) * 1e-3) / 1e9
+        roof["traffic_over_algorithmic"] = traffic / per_batch
+    if filter_bytes < CACHE_BYTES:
+        roof["note"] = "filters fit the 256 MB last-level cache: random reads are served by the cache"
+    return roof
+
+
+def minhash_roofline(wl, shingles, mh_ms, kernel):
+    """Roofline object of the MinHash stage.  `shingle_perm_per_s` is the
+    algorithmic rate; `achieved` prices each shingle hash and each evaluation
+    at the VALU lane-operations its k_minhash instance issues per unit
+    (counted by SQ_INSTS_VALU for this kernel version), so `frac` is the
+    stage's share of the INT32 VALU issue peak (None when the instance has
+    no counter profile)."""
+    import numpy as np
+
+    per_s = float(np.mean([sh * wl.num_perm / (t * 1e-3) for sh, t in zip(shingles, mh_ms)]))
+    counts = minhash_counts(minhash_ppl(wl.num_perm), 5)
+    roof = {"bound": "alu", "kernel": kernel, "achieved": None, "peak": INT32_VALU_PEAK / 1e12,
+            "unit": "TOPS (int32 VALU lane-ops/s)", "frac": None, "traffic": None,
+            "shingle_perm_per_s": per_s, "stage_ms_mean": float(np.mean(mh_ms))}
+    if counts:
+        ops_hash, ops_eval = counts[0], counts[1]
+        ach = float(np.mean([sh * (ops_hash + wl.num_perm * ops_eval) / (t * 1e-3)
+                             for sh, t in zip(shingles, mh_ms)]))
+        roof.update(achieved=ach / 1e12, frac=ach / INT32_VALU_PEAK,
+                    ops_per_shingle_hash=ops_hash, ops_per_evaluation=ops_eval)
+    return roof
+
+
 def _events(n):
     import torch
 
@@ -160,49 +262,51 @@ def _index(args, wl, lshbloom):
                              workspace_budget=budget)
 
 
-def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
-    """Plain per-batch form over a synthetic corpus: MinHash + query-insert per batch."""
-    B = wl.batch
-    n_batches = args.warmup + args.steps
-    if B * n_batches > wl.n_docs:
-        print(f"warmup + steps exceed the {wl.n_docs // B} full batches of the corpus", file=sys.stderr)
-        sys.exit(2)
-    n_docs = B * n_batches
-    t_gen = time.perf_counter()
-    corpus = synth.make_corpus(wl, device=dev, n_docs=n_docs)
+def make_stream(args, wl, torch, synth, dev):
+    """The workload's recipe drawn for warmup + steps batches (beyond the
+    configuration's own document count when more batches are asked for: the
+    near-duplicate sources then range over the whole longer stream)."""
+    n = wl.batch * (args.warmup + args.steps)
+    t = time.perf_counter()
+    corpus = synth.make_corpus(wl, device=dev, n_docs=n)
     torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
+    return corpus, time.perf_counter() - t
 
+
+def run_plain_device(args, wl, torch, np, lshbloom, corpus, steps, warmup, wide=False):
+    """Plain per-batch calls on inputs in HBM: MinHash + query-insert of each
+    batch on torch's current stream, each stage bracketed by HIP events."""
+    B = wl.batch
+    n_batches = warmup + steps
+    dev = corpus.offsets.device
     idx = _index(args, wl, lshbloom)
-    sigs = torch.empty((B, wl.num_perm), dtype=torch.int64 if args.wide else torch.int32, device=dev)
+    sigs = torch.empty((B, wl.num_perm), dtype=torch.int64 if wide else torch.int32, device=dev)
     flags = torch.empty((n_batches, B), dtype=torch.uint8, device=dev)
     offs = [corpus.offsets[b * B:(b + 1) * B + 1] for b in range(n_batches)]
-    lengths = torch.diff(corpus.offsets).cpu().numpy()
 
     def mh(b):
-        if args.wide:
+        if wide:
             idx.minhash61(offs[b], corpus.tokens, out=sigs)
         else:
             idx.minhash(offs[b], corpus.tokens, out=sigs)
 
     def qi(b):
-        if args.wide:
+        if wide:
             idx.query_insert_keys(idx.band_keys61(sigs), out=flags[b])
         else:
             idx.query_insert(sigs, out=flags[b])
 
-    for b in range(args.warmup):
+    for b in range(warmup):
         mh(b)
         qi(b)
     torch.cuda.synchronize()
-
     stream = torch.cuda.current_stream()
-    ev = _events(args.steps)
+    ev = _events(steps)
     bits0 = sum(idx.count_set_bits())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s in range(args.steps):
-        b = args.warmup + s
+    for s in range(steps):
+        b = warmup + s
         ev[s][0].record(stream)
         mh(b)
         ev[s][1].record(stream)
@@ -211,103 +315,106 @@ def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     new_bits = sum(idx.count_set_bits()) - bits0
-    assert idx.info()["device_status"] == 0
+    idx.sync()
+    mh_ms = [ev[s][0].elapsed_time(ev[s][1]) for s in range(steps)]
+    qi_ms = [ev[s][1].elapsed_time(ev[s][2]) for s in range(steps)]
+    out = {"elapsed": elapsed, "mh_ms": mh_ms, "qi_ms": qi_ms, "new_bits": new_bits, "k": idx.k,
+           "filter_bytes": idx.info()["filter_bytes"], "flags": flags}
+    idx.close()
+    return out
 
-    mh_ms = [ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)]
-    qi_ms = [ev[s][1].elapsed_time(ev[s][2]) for s in range(args.steps)]
-    timed = range(args.warmup, n_batches)
+
+def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
+    """Plain per-batch form over a synthetic stream already in HBM."""
+    B = wl.batch
+    corpus, t_gen = make_stream(args, wl, torch, synth, dev)
+    lengths = torch.diff(corpus.offsets).cpu().numpy()
+    r = run_plain_device(args, wl, torch, np, lshbloom, corpus, args.steps, args.warmup, wide=args.wide)
+    timed = range(args.warmup, args.warmup + args.steps)
     shingles = [shingle_count(lengths[b * B:(b + 1) * B]) for b in timed]
     tokens = [int(lengths[b * B:(b + 1) * B].sum()) for b in timed]
-    ops = [sh * (OPS_PER_SHINGLE_HASH + wl.num_perm * OPS_PER_SHINGLE_PERM) for sh in shingles]
-    mh_achieved = float(np.mean([o / (t * 1e-3) for o, t in zip(ops, mh_ms)]))
-    probes = B * wl.bands * idx.k
-    qi_bytes = qi_algorithmic_bytes(args.steps, B, probes, new_bits, wl.num_perm)
-    qi_achieved = qi_bytes / (float(np.sum(qi_ms)) * 1e-3)
-    minhash_roof = {
-        "bound": "alu",
-        "kernel": "k_minhash (incl. its 0xFFFFFFFF pre-fill)",
-        "achieved": mh_achieved / 1e12,
-        "peak": INT32_VALU_PEAK / 1e12,
-        "unit": "TOPS (int32 VALU lane-ops/s)",
-        "frac": mh_achieved / INT32_VALU_PEAK,
-        "traffic": float(np.mean(tokens)) * MINHASH_HBM_BYTES_PER_TOKEN if wl.num_perm == 128 else None,
-        "shingle_perm_per_s": float(np.mean([sh * wl.num_perm / (t * 1e-3) for sh, t in zip(shingles, mh_ms)])),
-    }
-    qi_roof = {
-        "bound": "hbm",
-        "kernel": "query-insert (all kernels of a batch's in-order test-and-set)",
-        "achieved": qi_achieved / 1e9,
-        "peak": 8000.0,
-        "unit": "GB/s",
-        "frac": qi_achieved / 8e12,
-        "traffic": None,
-        "algorithmic_bytes_per_batch": qi_bytes / args.steps,
-        "new_bits_per_batch": new_bits / args.steps,
-        "probes_per_s": float(np.mean([probes / (t * 1e-3) for t in qi_ms])),
-    }
-    if idx.info()["filter_bytes"] < CACHE_BYTES:
-        qi_roof["cache_resident_gather_per_s"] = CACHE_RESIDENT_GATHER_PER_S
-        qi_roof["probes_frac_of_cache_gather_rate"] = qi_roof["probes_per_s"] / CACHE_RESIDENT_GATHER_PER_S
+    probes = B * wl.bands * r["k"]
+    minhash_roof = minhash_roofline(wl, shingles, r["mh_ms"], "k_minhash (incl. its 0xFFFFFFFF pre-fill)")
+    qi_roof = qi_roofline(wl, args, B, probes, r["new_bits"], r["qi_ms"], r["filter_bytes"],
+                          None if args.wide else args.workload)
     if args.wide:
         # the wide kernel does more than the 32-bit operation count per
         # evaluation: its VALU fraction is not reported on that count
-        minhash_roof = dict(minhash_roof, kernel="k_minhash (wide values)", achieved=None, frac=None, traffic=None)
+        minhash_roof = dict(minhash_roof, kernel="k_minhash (wide values)", achieved=None, frac=None)
         qi_roof = dict(qi_roof, kernel="band keys of wide values + query-insert from keys")
-    dominant = minhash_roof if np.mean(mh_ms) >= np.mean(qi_ms) else qi_roof
+    dominant = minhash_roof if np.mean(r["mh_ms"]) >= np.mean(r["qi_ms"]) else qi_roof
     res = {
-        "value": args.steps * B / elapsed,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "value": args.steps * B / r["elapsed"],
+        "ms_per_step": r["elapsed"] * 1e3 / args.steps,
         "docs_timed": args.steps * B,
         "tokens_per_step": float(np.mean(tokens)),
-        "text_GBps": float(np.sum(tokens)) * 4 / elapsed / 1e9,
-        "stage_ms": {"minhash": float(np.mean(mh_ms)), "query_insert": float(np.mean(qi_ms))},
+        "text_GBps": float(np.sum(tokens)) * 4 / r["elapsed"] / 1e9,
+        "stage_ms": {"minhash": float(np.mean(r["mh_ms"])), "query_insert": float(np.mean(r["qi_ms"]))},
         "roofline": dominant,
-        "other_rooflines": [r for r in (minhash_roof, qi_roof) if r is not dominant],
-        "flagged_frac": float(flags[args.warmup:].float().mean().item()),
+        "other_rooflines": [x for x in (minhash_roof, qi_roof) if x is not dominant],
+        "flagged_frac": float(r["flags"][args.warmup:].float().mean().item()),
         "corpus_gen_s": t_gen,
     }
     if args.wide:
         res["variant"] = "wide (61-bit MinHash values, band keys of them, query-insert from keys)"
-    return res, corpus, idx
+    h_off = corpus.offsets.cpu().numpy()
+    h_tok = corpus.tokens[: int(h_off[min(len(h_off) - 1, 8 * args.cpu_sample_docs)])].cpu().numpy()
+    return res, (h_off, h_tok)
 
 
 def run_batched(args, wl, torch, np, lshbloom, synth, dev):
-    """Batched form: host CSR batches through the pipeline, against the plain
-    per-batch calls fed the same host batches (H2D, MinHash, query-insert,
-    D2H, one batch at a time), each with its own index."""
+    """Batched form (the headline): host CSR batches through the pipeline,
+    beside the plain per-batch calls fed the same host batches (H2D, MinHash,
+    query-insert, D2H, one batch at a time) and plain calls on the same
+    batches already in HBM, each with its own index."""
     B = wl.batch
     n_batches = args.warmup + args.steps
-    if B * n_batches > wl.n_docs:
-        print(f"warmup + steps exceed the {wl.n_docs // B} full batches of the corpus", file=sys.stderr)
-        sys.exit(2)
-    t_gen = time.perf_counter()
-    corpus = synth.make_corpus(wl, device=dev, n_docs=B * n_batches)
-    h_off = corpus.offsets.cpu().pin_memory()
-    h_tok = corpus.tokens.cpu().pin_memory()
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
+    corpus, t_gen = make_stream(args, wl, torch, synth, dev)
     lengths = torch.diff(corpus.offsets).cpu().numpy()
-    max_tok = int(max(lengths[b * B:(b + 1) * B].sum() for b in range(n_batches)))
+
+    # plain calls on inputs in HBM (the device-resident rate)
+    dres = run_plain_device(args, wl, torch, np, lshbloom, corpus, args.steps, args.warmup)
+    dev_flags = dres.pop("flags")[args.warmup:].cpu()
+
+    # host copies of the stream (pinned, so the pipeline moves tokens by DMA)
+    t_pin = time.perf_counter()
+    h_off = torch.empty(corpus.offsets.numel(), dtype=torch.int64, pin_memory=True)
+    h_off.copy_(corpus.offsets)
+    h_tok = torch.empty(corpus.tokens.numel(), dtype=torch.int32, pin_memory=True)
+    h_tok.copy_(corpus.tokens)
+    torch.cuda.synchronize()
+    t_pin = time.perf_counter() - t_pin
     del corpus
+    torch.cuda.empty_cache()
+    max_tok = int(max(lengths[b * B:(b + 1) * B].sum() for b in range(n_batches)))
+    offs = [h_off[b * B:(b + 1) * B + 1].clone().pin_memory() for b in range(n_batches)]
 
     # batched form
     idx = _index(args, wl, lshbloom)
     pl = lshbloom.Pipeline(idx, max_docs=B, max_tokens=max_tok, use_graph=True, autotune=True)
     flags = torch.zeros((n_batches, B), dtype=torch.uint8).pin_memory()
-    offs = [h_off[b * B:(b + 1) * B + 1].clone().pin_memory() for b in range(n_batches)]
     for b in range(args.warmup):
         pl.wait(pl.submit(offs[b], h_tok, flags[b]))
+    inf0 = pl.info()
+    bits0 = sum(idx.count_set_bits())
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     tickets = [pl.submit(offs[b], h_tok, flags[b]) for b in range(args.warmup, n_batches)]
     for t in tickets:
         pl.wait(t)
     elapsed = time.perf_counter() - t0
-    info = pl.info()
+    torch.cuda.synchronize()
+    inf1 = pl.info()
+    new_bits = sum(idx.count_set_bits()) - bits0
     pl.close()
-    assert idx.info()["device_status"] == 0
+    idx.sync()
+    filter_bytes = idx.info()["filter_bytes"]
+    k = idx.k
     batched_flags = flags[args.warmup:].clone()
     idx.close()
-    del idx
+    nb = inf1["timed_batches"] - inf0["timed_batches"]
+    qi_ms_mean = (inf1["qi_ms_total"] - inf0["qi_ms_total"]) / nb
+    mh_ms_mean = (inf1["minhash_ms_total"] - inf0["minhash_ms_total"]) / nb
 
     # plain per-batch calls on the same host batches
     idx = _index(args, wl, lshbloom)
@@ -328,10 +435,21 @@ def run_batched(args, wl, torch, np, lshbloom, synth, dev):
     for b in range(args.warmup, n_batches):
         plain(b)
     plain_elapsed = time.perf_counter() - t1
-    assert idx.info()["device_status"] == 0
-    same = bool(torch.equal(batched_flags, pflags[args.warmup:]))
+    idx.sync()
     idx.close()
-    tokens = [int(lengths[b * B:(b + 1) * B].sum()) for b in range(args.warmup, n_batches)]
+
+    timed = range(args.warmup, n_batches)
+    tokens = [int(lengths[b * B:(b + 1) * B].sum()) for b in timed]
+    shingles = [shingle_count(lengths[b * B:(b + 1) * B]) for b in timed]
+    probes = B * wl.bands * k
+    qi_roof = qi_roofline(wl, args, B, probes, new_bits, [qi_ms_mean] * args.steps, filter_bytes, args.workload)
+    qi_roof["timing"] = ("HIP events on the pipeline's query-insert stream around each batch's query-insert "
+                         f"kernels, mean over the {nb} timed batches")
+    mh_roof = minhash_roofline(wl, shingles, [mh_ms_mean] * args.steps,
+                               "k_minhash, one launch per length bucket (incl. the signature pre-fill)")
+    mh_roof["timing"] = "HIP events on the pipeline's slot streams around each batch's MinHash stage"
+    dominant, other = (qi_roof, mh_roof) if qi_ms_mean >= mh_ms_mean else (mh_roof, qi_roof)
+    same = bool(torch.equal(batched_flags, pflags[args.warmup:])) and bool(torch.equal(batched_flags, dev_flags))
     res = {
         "value": args.steps * B / elapsed,
         "ms_per_step": elapsed * 1e3 / args.steps,
@@ -339,15 +457,26 @@ def run_batched(args, wl, torch, np, lshbloom, synth, dev):
         "tokens_per_step": float(np.mean(tokens)),
         "text_GBps": float(np.sum(tokens)) * 4 / elapsed / 1e9,
         "form": "batched (host CSR in, host flags out; length buckets, 2 overlapping slots, hipGraph, autotuner)",
+        "stage_ms": {"minhash": mh_ms_mean, "query_insert": qi_ms_mean},
+        "roofline": dominant,
+        "other_rooflines": [other],
         "plain_per_batch_from_host": {"value": args.steps * B / plain_elapsed,
-                                      "ms_per_step": plain_elapsed * 1e3 / args.steps},
+                                      "ms_per_step": plain_elapsed * 1e3 / args.steps,
+                                      "form": "per batch: H2D copy, MinHash, query-insert, D2H flags, synchronise"},
+        "plain_device_resident": {"value": args.steps * B / dres["elapsed"],
+                                  "ms_per_step": dres["elapsed"] * 1e3 / args.steps,
+                                  "stage_ms": {"minhash": float(np.mean(dres["mh_ms"])),
+                                               "query_insert": float(np.mean(dres["qi_ms"]))},
+                                  "form": "per batch: MinHash + query-insert on inputs already in HBM"},
         "speedup_vs_plain_from_host": plain_elapsed / elapsed,
-        "flags_identical_to_plain": same,
-        "pipeline": info,
+        "flags_identical_across_forms": same,
+        "pipeline": {k_: v for k_, v in inf1.items() if k_ not in ("minhash_ms_total", "qi_ms_total")},
         "flagged_frac": float(batched_flags.float().mean().item()),
         "corpus_gen_s": t_gen,
+        "host_copy_s": t_pin,
     }
-    return res, None, None
+    n_cpu = min(len(h_off) - 1, 8 * args.cpu_sample_docs)
+    return res, (h_off.numpy(), h_tok[: int(h_off[n_cpu])].numpy())
 
 
 def _scores(flags, truth):
@@ -380,14 +509,8 @@ def run_fidelity(args, wl, torch, np, lshbloom, synth, dev):
     time and size."""
     B = wl.batch
     n_batches = args.warmup + args.steps
-    if B * n_batches > wl.n_docs:
-        print(f"warmup + steps exceed the {wl.n_docs // B} full batches of the corpus", file=sys.stderr)
-        sys.exit(2)
     n = B * n_batches
-    t_gen = time.perf_counter()
-    corpus = synth.make_corpus(wl, device=dev, n_docs=n)
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t_gen
+    corpus, t_gen = make_stream(args, wl, torch, synth, dev)
     truth = np.asarray(corpus.is_dup[:n]).astype(bool)
 
     idx = _index(args, wl, lshbloom)
@@ -429,11 +552,13 @@ def run_fidelity(args, wl, torch, np, lshbloom, synth, dev):
         "corpus_gen_s": t_gen,
     }
     ex.close()
-    return res, None, None
+    return res, None
 
 
 def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
     """Filter-scale query-insert: batches of precomputed signatures only."""
+    if args.full_stream:
+        return run_signature_stream(args, wl, torch, np, lshbloom, synth, dev)
     B = wl.batch
     n_batches = args.warmup + args.steps
     idx = _index(args, wl, lshbloom)
@@ -460,11 +585,9 @@ def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     new_bits = sum(idx.count_set_bits()) - bits0
-    assert idx.info()["device_status"] == 0
+    idx.sync()
     qi_ms = [ev[s][0].elapsed_time(ev[s][1]) for s in range(args.steps)]
     probes = B * wl.bands * idx.k
-    qi_bytes = qi_algorithmic_bytes(args.steps, B, probes, new_bits, wl.num_perm)
-    ach = qi_bytes / (float(np.sum(qi_ms)) * 1e-3)
     rep, _ = synth.signature_repeat_info(args.warmup * B, args.steps * B, wl.bands, B, ex["repeat_frac"],
                                          ex["in_batch_frac"], wl.corpus_seed, device=dev)
     fl = flags[args.warmup:].reshape(-1)
@@ -473,20 +596,106 @@ def run_signatures(args, wl, torch, np, lshbloom, synth, dev):
         "ms_per_step": elapsed * 1e3 / args.steps,
         "docs_timed": args.steps * B,
         "stage_ms": {"query_insert": float(np.mean(qi_ms))},
-        "roofline": {
-            "bound": "hbm",
-            "kernel": "query-insert (all kernels of a batch's in-order test-and-set)",
-            "achieved": ach / 1e9, "peak": 8000.0, "unit": "GB/s", "frac": ach / 8e12, "traffic": None,
-            "algorithmic_bytes_per_batch": qi_bytes / args.steps,
-            "new_bits_per_batch": new_bits / args.steps,
-            "probes_per_s": float(np.mean([probes / (t * 1e-3) for t in qi_ms])),
-        },
+        "roofline": qi_roofline(wl, args, B, probes, new_bits, qi_ms, idx.info()["filter_bytes"], "c4"),
         "repeats_flagged": float(fl[rep].float().mean().item()),
         "non_repeats_flagged": float(fl[~rep].float().mean().item()),
         "filter_bytes": idx.info()["filter_bytes"],
         "sig_gen_s": t_gen,
     }
-    return res, None, idx
+    idx.close()
+    return res, None
+
+
+def run_signature_stream(args, wl, torch, np, lshbloom, synth, dev):
+    """The whole filter-scale stream: wl.n_docs signatures in batches of
+    wl.batch, generated on the device one batch ahead of its query-insert.
+    Every repeat (a band copied from an earlier signature) must be flagged;
+    the flags of the other signatures are false positives, whose count is
+    compared with the p_eff composition law (Section 4.3): a unique signature
+    arriving when band j's filter has X_j of its m bits set is flagged with
+    probability 1 - prod_j (1 - (X_j / m)^k), X_j read every `every` batches
+    and interpolated linearly in between."""
+    import math
+
+    B = wl.batch
+    n_batches = wl.n_docs // B
+    ex = wl.extra
+    idx = _index(args, wl, lshbloom)
+    k, m = idx.k, idx.m_bits
+    every = 25
+    flags = torch.empty(B, dtype=torch.uint8, device=dev)
+    missed = torch.zeros((), dtype=torch.int64, device=dev)
+    fp_flags = torch.zeros((), dtype=torch.int64, device=dev)
+    n_rep = torch.zeros((), dtype=torch.int64, device=dev)
+    expect = 0.0
+    reps_seen = 0
+    fill = [np.zeros(wl.bands)]
+    stream = torch.cuda.current_stream()
+    qi_ms = []
+    t0 = time.perf_counter()
+    nxt = synth.signature_batch(0, B, wl.num_perm, wl.bands, wl.rows, B, ex["repeat_frac"], ex["in_batch_frac"],
+                                wl.corpus_seed, device=dev)
+    for b in range(n_batches):
+        sigs = nxt
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        idx.query_insert(sigs, out=flags)
+        e1.record(stream)
+        qi_ms.append((e0, e1))
+        rep, _ = synth.signature_repeat_info(b * B, B, wl.bands, B, ex["repeat_frac"], ex["in_batch_frac"],
+                                             wl.corpus_seed, device=dev)
+        missed += (flags[rep] == 0).sum()
+        fp_flags += flags[~rep].sum(dtype=torch.int64)
+        n_rep += rep.sum()
+        if b + 1 < n_batches:
+            nxt = synth.signature_batch((b + 1) * B, B, wl.num_perm, wl.bands, wl.rows, B, ex["repeat_frac"],
+                                        ex["in_batch_frac"], wl.corpus_seed, device=dev)
+        if (b + 1) % every == 0 or b + 1 == n_batches:
+            x1 = np.array(idx.count_set_bits(), dtype=np.float64)
+            x0 = fill[-1]
+            nb = (b + 1) - (len(fill) - 1) * every
+            reps_now = int(n_rep.item())
+            uniq = B * nb - (reps_now - reps_seen)
+            reps_seen = reps_now
+            # expected false flags of the unique signatures of these batches
+            # (midpoint rule over the interval's fill)
+            steps = 64
+            p_sum = 0.0
+            for q in range(steps):
+                x = x0 + (x1 - x0) * (q + 0.5) / steps
+                p_band = (x / m) ** k
+                p_sum += -math.expm1(float(np.sum(np.log1p(-p_band))))
+            expect += p_sum / steps * uniq
+            fill.append(x1)
+            print(f"[c4 stream] {b + 1}/{n_batches} batches, {time.perf_counter() - t0:.0f} s, "
+                  f"fill {x1.mean() / m:.4f}, missed repeats {int(missed.item())}, "
+                  f"false flags {int(fp_flags.item())} (expected so far {expect:.3f})", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    idx.sync()
+    ms = [a_.elapsed_time(b_) for a_, b_ in qi_ms]
+    n_unique = wl.n_docs - int(n_rep.item())
+    obs = int(fp_flags.item())
+    # two-sided 99.9% Poisson interval for the observed count given the expectation
+    from scipy.stats import poisson
+    lo, hi = poisson.ppf(0.0005, expect), poisson.ppf(0.9995, expect)
+    res = {
+        "value": wl.n_docs / elapsed,
+        "ms_per_step": elapsed * 1e3 / n_batches,
+        "docs_timed": wl.n_docs,
+        "stage_ms": {"query_insert": float(np.mean(ms))},
+        "full_stream": {
+            "signatures": wl.n_docs, "batches": n_batches, "repeats": int(n_rep.item()),
+            "repeats_not_flagged": int(missed.item()), "unique": n_unique,
+            "unique_flagged": obs, "unique_flagged_expected_p_eff": expect,
+            "poisson_99_9_interval": [float(lo), float(hi)],
+            "p9_holds": bool(lo <= obs <= hi), "final_fill": float(fill[-1].mean() / m),
+            "elapsed_s_incl_generation": elapsed, "query_insert_ms_mean": float(np.mean(ms)),
+        },
+        "filter_bytes": idx.info()["filter_bytes"],
+    }
+    idx.close()
+    return res, None
 
 
 def run_serve(args, wl, torch, np, lshbloom, synth, dev):
@@ -500,7 +709,7 @@ def run_serve(args, wl, torch, np, lshbloom, synth, dev):
     from paper_2411_04257_amd import serve
 
     loads = [float(x) for x in args.loads.split(",")]
-    n_reqs = [int(max(40, min(1000, ld / 100))) for ld in loads]
+    n_reqs = [args.requests for _ in loads]
     preload_n = wl.extra["preload"] if args.preload is None else args.preload
     rng = np.random.default_rng(wl.corpus_seed)
     warm = serve.poisson_requests(8, 10000.0, wl.extra["req_min"], wl.extra["req_max"], 0, rng)
@@ -536,8 +745,10 @@ def run_serve(args, wl, torch, np, lshbloom, synth, dev):
         for idx in (idx_b, idx_p):
             idx.write_filters(snap, docs_inserted=preload_n)
         torch.cuda.synchronize()
-        rb = srv.run(copy.deepcopy(reqs), h_off, h_tok, fb).summary()
-        rp = plain.run(copy.deepcopy(reqs), h_off, h_tok, fp_).summary()
+        print(f"[c5] offered {ld:.0f} docs/s: {len(reqs)} requests, continuous batching", file=sys.stderr, flush=True)
+        rb = srv.run(copy.deepcopy(reqs), h_off, h_tok, fb, progress_s=30.0).summary()
+        print(f"[c5] offered {ld:.0f} docs/s: one request per batch", file=sys.stderr, flush=True)
+        rp = plain.run(copy.deepcopy(reqs), h_off, h_tok, fp_, progress_s=30.0).summary()
         if nr is None:
             continue
         lo, hi = reqs[0].lo, reqs[-1].hi
@@ -561,7 +772,7 @@ def run_serve(args, wl, torch, np, lshbloom, synth, dev):
     }
     idx_b.close()
     idx_p.close()
-    return res, None, None
+    return res, None
 
 
 def probe_hbm(torch, gb):
@@ -621,8 +832,9 @@ DESCRIPTIONS = {
     "c2": "plain method on GPU: 1M-doc synthetic corpus (Zipf(1.1)/50k-vocab uint32 tokens, lognormal lengths "
           "median 3000 sigma 0.8 cap 50000, 20% near-dups J 0.6-0.95), 5-shingles, num_perm 128, 16 bands x 8 rows, "
           "filters n=1M fp=1e-6, batches of 65,536",
-    "c3": "10M-doc synthetic corpus with Pareto(1.5, min 20, cap 200k) lengths, Zipf(1.1)/50k vocab, 25% near-dups; "
-          "num_perm 256, 32 bands x 8 rows, filters n=100M fp=1e-8 (15.3 GB), batches of 1M",
+    "c3": "batched-form configuration (c3): synthetic corpus with Pareto(1.5, min 20, cap 200k) lengths, "
+          "Zipf(1.1)/50k vocab, 25% near-dups; num_perm 256, 32 bands x 8 rows, filters n=100M fp=1e-8 per band "
+          "(15.3 GB), batches of 1M",
     "c4": "filter-scale query-insert: 1B-signature stream of uniform uint32 (256 wide) with 30% one-band repeats, "
           "32 bands x 8 rows, filters n=1e9 fp=1e-10 per band (191.7 GB in HBM), batches of 1M (timed prefix)",
     "c5": "serving: Poisson arrivals of 1-4096-document requests (log-uniform), lognormal lengths median 2000 "
@@ -630,6 +842,18 @@ DESCRIPTIONS = {
           "documents (num_perm 128, 16 bands x 8 rows, fp 1e-8 per band, 7.7 GB); continuous batching with "
           "HBM-budget admission vs one request per batch",
 }
+
+
+def stream_note(args, wl) -> str:
+    if args.workload not in ("c2", "c3"):
+        return ""
+    n = wl.batch * (args.warmup + args.steps)
+    note = (f"; stream: {args.warmup + args.steps} full batches ({n:,} documents: {args.warmup} warmup, "
+            f"{args.steps} timed) drawn from this recipe")
+    if n > wl.n_docs:
+        note += (f", past the configuration's {wl.n_docs:,} documents (near-duplicate sources range over the "
+                 f"whole stream; the filters are sized for n = {wl.expected_n:,})")
+    return note
 
 
 def main():
@@ -654,24 +878,24 @@ def main():
         wl = dataclasses.replace(wl, batch=args.batch)
     higher = True
     if args.workload == "c4":
-        res, corpus, idx = run_signatures(args, wl, torch, np, lshbloom, synth, dev)
+        res, host_stream = run_signatures(args, wl, torch, np, lshbloom, synth, dev)
         metric = "signatures/sec query-insert (band Bloom), bit-exact flags"
         unit = "sigs/s"
     elif args.workload == "c5":
-        res, corpus, idx = run_serve(args, wl, torch, np, lshbloom, synth, dev)
+        res, host_stream = run_serve(args, wl, torch, np, lshbloom, synth, dev)
         metric = "p99 serve latency (ms) at the highest offered load, continuous batching"
         unit = "ms"
         higher = False
     elif args.form == "fidelity":
-        res, corpus, idx = run_fidelity(args, wl, torch, np, lshbloom, synth, dev)
+        res, host_stream = run_fidelity(args, wl, torch, np, lshbloom, synth, dev)
         metric = "F1 gap, LSHBloom minus exact MinHashLSH, on the same signatures (near-dup labels)"
         unit = "F1"
     elif args.form == "batched":
-        res, corpus, idx = run_batched(args, wl, torch, np, lshbloom, synth, dev)
+        res, host_stream = run_batched(args, wl, torch, np, lshbloom, synth, dev)
         metric = "docs/sec end-to-end (MinHash+band Bloom), bit-exact flags"
         unit = "docs/s"
     else:
-        res, corpus, idx = run_corpus(args, wl, torch, np, lshbloom, synth, dev)
+        res, host_stream = run_corpus(args, wl, torch, np, lshbloom, synth, dev)
         metric = "docs/sec end-to-end (MinHash+band Bloom), bit-exact flags"
         unit = "docs/s"
 
@@ -689,7 +913,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": DESCRIPTIONS[args.workload],
+            "workload": DESCRIPTIONS[args.workload] + stream_note(args, wl),
             "global_batch": wl.batch if args.workload != "c5" else None,
             "docs_timed": res.pop("docs_timed"),
             "parallelism": "single-gpu",
@@ -704,8 +928,9 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_bytes"] = args.copy_bytes
-    if corpus is not None and not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, corpus, min(args.cpu_sample_docs, corpus.n_docs))
+    if host_stream is not None and not args.no_cpu_baseline:
+        h_off, h_tok = host_stream
+        out["cpu_baseline"] = cpu_baseline(wl, h_off, h_tok, min(args.cpu_sample_docs, len(h_off) - 1))
     print(json.dumps(out), flush=True)
 
 

@@ -59,6 +59,15 @@
  * failure.  Invalid arguments are rejected before anything is launched.  A
  * device error inside a filter-changing call poisons the handle (its filters
  * may be half-written): every later call on it returns LSHBLOOM_EPOISONED.
+ * The kernels also check their own bookkeeping (record totals, table
+ * capacities, that every probed clear bit was registered) and raise bits of
+ * a device status word when it fails; each filter-changing call ends with an
+ * asynchronous copy of that word to host memory.  The first call on the
+ * handle that finds it nonzero (at the latest, the first one made after the
+ * host has waited for the failing call: lshbloom_sync, lshbloom_pipeline_wait
+ * or _poll, lshbloom_count_set_bits, lshbloom_save, or a read_filters into
+ * pageable memory) poisons the handle and returns LSHBLOOM_EDEVICE; the
+ * flags of calls from the failing one on are not to be trusted.
  * Device-side data (offsets, tokens) is trusted: offsets must be
  * non-decreasing and in bounds of d_tokens.
  *
@@ -84,6 +93,7 @@ enum {
   LSHBLOOM_EHIP = -3,      /* HIP runtime error; message in last_error */
   LSHBLOOM_EPOISONED = -4, /* an earlier device error left the filters indeterminate */
   LSHBLOOM_EIO = -5,       /* a file could not be opened, read or written */
+  LSHBLOOM_EDEVICE = -6,   /* a kernel reported an internal inconsistency; the handle is poisoned */
 };
 
 /* Limits of this implementation. */
@@ -250,6 +260,12 @@ int lshbloom_count_set_bits(lshbloom_t *h, uint64_t *out, lshbloom_stream_t stre
 /* Parameters, sizes and counters of the handle. */
 int lshbloom_info(const lshbloom_t *h, lshbloom_info_t *out);
 
+/* Wait for the handle's outstanding calls, then report their outcome:
+ * LSHBLOOM_OK, LSHBLOOM_EDEVICE if a kernel raised the device status word
+ * (the handle is then poisoned), LSHBLOOM_EPOISONED if it already was, or
+ * LSHBLOOM_EHIP for a runtime error. */
+int lshbloom_sync(lshbloom_t *h);
+
 /* Per-band rate p that gives an effective rate p_eff over `bands` bands,
  * p = 1 - (1 - p_eff)^(1/bands) (Section 4.3). */
 double lshbloom_p_band_from_eff(double p_eff, uint32_t bands);
@@ -285,6 +301,9 @@ typedef struct lshbloom_pipeline_info {
   float tune_best_ms;          /* MinHash time of the chosen configuration on the tuning batch */
   uint64_t batches;
   uint64_t graph_launches, graph_updates, graph_instantiations;
+  uint64_t timed_batches;      /* non-empty batches collected so far */
+  double minhash_ms_total;     /* their MinHash stages (pre-fill + MinHash launches), summed, in ms */
+  double qi_ms_total;          /* their query-insert kernels, summed, in ms (HIP events on the query-insert stream) */
 } lshbloom_pipeline_info_t;
 
 /* Create a pipeline that feeds `h` (which must outlive it).  It owns two
@@ -303,14 +322,16 @@ lshbloom_pipeline_t *lshbloom_pipeline_create(lshbloom_t *h, const lshbloom_pipe
 int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offsets, const uint32_t *h_tokens,
                                  int64_t n_docs, uint8_t *h_flags);
 
-/* Block until the batch of `ticket` is done and its flags are in its h_flags. */
+/* Block until the batch of `ticket` is done and its flags are in its h_flags.
+ * Returns LSHBLOOM_EDEVICE (flags delivered but not to be trusted; the handle
+ * is poisoned) when a kernel of the handle reported an inconsistency. */
 int lshbloom_pipeline_wait(lshbloom_pipeline_t *pl, int64_t ticket);
 
 /* Non-blocking: 1 if the batch of `ticket` is done (its flags are then in
  * its h_flags), 0 if not yet, negative on error. */
 int lshbloom_pipeline_poll(lshbloom_pipeline_t *pl, int64_t ticket);
 
-/* Chosen buckets, grid sizes and graph counters. */
+/* Chosen buckets, grid sizes, graph counters and stage times. */
 int lshbloom_pipeline_info(const lshbloom_pipeline_t *pl, lshbloom_pipeline_info_t *out);
 
 /* Finish outstanding batches (delivering their flags) and free the pipeline. */

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "../../include/lshbloom.h"
@@ -24,6 +25,7 @@ struct lshbloom {
   uint64_t *d_masks = nullptr;
   uint8_t *d_hitb = nullptr;
   uint32_t *d_status = nullptr;
+  uint32_t *h_status = nullptr;  // pinned host copy of d_status, refreshed at the end of every query-insert call
   uint64_t *d_count = nullptr;  // per-band set-bit counts [bands]
   uint64_t chunk_docs = 0;
   uint64_t workspace_bytes = 0;
@@ -40,10 +42,12 @@ struct lshbloom {
   int cus = 0;            // compute units of the device
   hipEvent_t last = nullptr;
   bool has_last = false;
-  bool poisoned = false;
+  std::atomic<bool> poisoned{false};
   uint64_t docs_inserted = 0;
   uint64_t calls = 0;
   int64_t fault_at = -1;  // host-forced failure of the n-th filter call (testing)
+  uint64_t qi_calls = 0;
+  int64_t status_at = -1;  // host-forced device status report by the n-th query-insert call (testing)
   std::mutex mu;
 };
 
@@ -55,7 +59,13 @@ int fail_hip(lshbloom *h, hipError_t e, const char *what);
 // and record the end of that work as the handle's new last call.
 hipError_t begin_ordered(lshbloom *h, hipStream_t s);
 hipError_t end_ordered(lshbloom *h, hipStream_t s);
+// LSHBLOOM_OK, or the error a call on h must return: EDEVICE the first time
+// the host copy of the device status word is seen nonzero (the handle is
+// then poisoned), EPOISONED afterwards.
 int check_ready(lshbloom *h);
+// End of a query-insert call on s: the device status word's copy to host
+// memory (and, for testing, a host-forced status report).
+hipError_t finish_qi(lshbloom *h, hipStream_t s);
 // Enqueue the in-order query-insert of n signatures on s (no locking, no
 // ordering events, no counters); the algorithm follows the handle's mode.
 // Returns LSHBLOOM_OK or an error code (message set, handle poisoned on a

@@ -121,6 +121,7 @@ void free_all(lshbloom *h) {
   if (h->d_masks) (void)hipFree(h->d_masks);
   if (h->d_hitb) (void)hipFree(h->d_hitb);
   if (h->d_status) (void)hipFree(h->d_status);
+  if (h->h_status) (void)hipHostFree(h->h_status);
   if (h->d_count) (void)hipFree(h->d_count);
   if (h->d_counts1) (void)hipFree(h->d_counts1);
   if (h->d_bstart) (void)hipFree(h->d_bstart);
@@ -153,11 +154,25 @@ int check_ready(lshbloom *h) {
     set_err("null handle");
     return LSHBLOOM_EINVAL;
   }
+  const uint32_t st = h->h_status ? __atomic_load_n(h->h_status, __ATOMIC_ACQUIRE) : 0u;
+  if (st != 0 && !h->poisoned.exchange(true)) {
+    set_err("a kernel reported an internal inconsistency (device status 0x%x); the handle is poisoned", st);
+    return LSHBLOOM_EDEVICE;
+  }
   if (h->poisoned) {
     set_err("handle poisoned by an earlier device error; filters are indeterminate");
     return LSHBLOOM_EPOISONED;
   }
   return LSHBLOOM_OK;
+}
+
+hipError_t finish_qi(lshbloom *h, hipStream_t s) {
+  h->qi_calls += 1;
+  if (h->status_at >= 0 && (int64_t)h->qi_calls == h->status_at) {
+    const hipError_t e = lb::launch_fill_u32(h->d_status, 1, 16u, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipMemcpyAsync(h->h_status, h->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
 }
 
 }  // namespace lbh
@@ -369,6 +384,7 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   h->words_per_band = h->m_bits / 64;
   h->k = k;
   if (const char *fa = std::getenv("LSHBLOOM_FAULT_AT")) h->fault_at = std::atoll(fa);
+  if (const char *sa = std::getenv("LSHBLOOM_STATUS_AT")) h->status_at = std::atoll(sa);
 
   // Coefficient stream.
   SplitMix64 rng{prm.seed};
@@ -496,6 +512,13 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   }
   LB_ALLOC(h->d_coef, prm.num_perm * sizeof(lb::PermCoef));
   LB_ALLOC(h->d_status, 256);
+  if ((e = hipHostMalloc((void **)&h->h_status, 64, hipHostMallocDefault)) != hipSuccess) {
+    fail_hip(nullptr, e, "create: pinned status word");
+    free_all(h);
+    delete h;
+    return nullptr;
+  }
+  *h->h_status = 0;
   LB_ALLOC(h->d_count, (size_t)prm.bands * 8);
 #undef LB_ALLOC
   if ((e = hipMemcpy(h->d_coef, coef.data(), coef.size() * sizeof(lb::PermCoef), hipMemcpyHostToDevice)) !=
@@ -578,7 +601,8 @@ int lshbloom_query_insert(lshbloom_t *h, const uint32_t *d_sigs, int64_t n_docs,
   if (e != hipSuccess) return fail_hip(h, e, "query_insert: stream wait");
   rc = lbh::qi_enqueue(h, d_sigs, n_docs, d_flags, s);
   if (rc) return rc;
-  e = end_ordered(h, s);
+  e = lbh::finish_qi(h, s);
+  if (e == hipSuccess) e = end_ordered(h, s);
   if (e != hipSuccess) return fail_hip(h, e, "query_insert: event");
   h->docs_inserted += (uint64_t)n_docs;
   return LSHBLOOM_OK;
@@ -631,7 +655,8 @@ int lshbloom_query_insert_noalloc(lshbloom_t *h, const uint32_t *d_sigs, int64_t
     e = lb::launch_query_insert_chunk(a, slots, s);
     if (e != hipSuccess) return fail_hip(h, e, "query_insert_noalloc: launch");
   }
-  e = end_ordered(h, s);
+  e = lbh::finish_qi(h, s);
+  if (e == hipSuccess) e = end_ordered(h, s);
   if (e != hipSuccess) return fail_hip(h, e, "query_insert_noalloc: event");
   h->docs_inserted += (uint64_t)n_docs;
   return LSHBLOOM_OK;
@@ -762,7 +787,8 @@ int lshbloom_query_insert_keys(lshbloom_t *h, const uint64_t *d_keys, int64_t n_
   if (e != hipSuccess) return fail_hip(h, e, "query_insert_keys: stream wait");
   rc = lbh::qi_enqueue(h, nullptr, n_docs, d_flags, s, d_keys);
   if (rc) return rc;
-  e = end_ordered(h, s);
+  e = lbh::finish_qi(h, s);
+  if (e == hipSuccess) e = end_ordered(h, s);
   if (e != hipSuccess) return fail_hip(h, e, "query_insert_keys: event");
   h->docs_inserted += (uint64_t)n_docs;
   return LSHBLOOM_OK;
@@ -966,6 +992,16 @@ int lshbloom_write_filters(lshbloom_t *h, const void *src, uint64_t offset, uint
   if (e != hipSuccess) return fail_hip(h, e, "write_filters: event");
   if (docs_inserted != UINT64_MAX) h->docs_inserted = docs_inserted;
   return LSHBLOOM_OK;
+}
+
+int lshbloom_sync(lshbloom_t *h) {
+  if (!h) return check_ready(h);
+  std::lock_guard<std::mutex> lk(h->mu);
+  if (h->has_last) {
+    const hipError_t e = hipEventSynchronize(h->last);
+    if (e != hipSuccess) return fail_hip(h, e, "sync");
+  }
+  return check_ready(h);
 }
 
 int lshbloom_info(const lshbloom_t *hc, lshbloom_info_t *out) {

@@ -42,6 +42,9 @@ constexpr uint32_t kMaxBuckets = 4;
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t copied = nullptr, mh_done = nullptr, done = nullptr;
+  // timing events around the batch's MinHash stage (slot stream) and its
+  // query-insert kernels (query-insert stream)
+  hipEvent_t mh_t0 = nullptr, mh_t1 = nullptr, qi_t0 = nullptr, qi_t1 = nullptr;
   int64_t *h_desc = nullptr;     // pinned bucket descriptors
   uint32_t *h_tokens = nullptr;  // pinned token staging (used when the caller's buffer is pageable)
   uint8_t *h_flags = nullptr;    // pinned flags
@@ -75,6 +78,8 @@ struct lshbloom_pipeline {
   bool tuned = false;
   uint64_t graph_launches = 0, graph_updates = 0, graph_instantiations = 0;
   float tune_best_ms = 0.f;
+  uint64_t timed_batches = 0;
+  double minhash_ms_total = 0.0, qi_ms_total = 0.0;
   std::mutex mu;
 };
 
@@ -313,6 +318,8 @@ void free_pipeline(lshbloom_pipeline *pl) {
     if (S.copied) (void)hipEventDestroy(S.copied);
     if (S.mh_done) (void)hipEventDestroy(S.mh_done);
     if (S.done) (void)hipEventDestroy(S.done);
+    for (hipEvent_t ev : {S.mh_t0, S.mh_t1, S.qi_t0, S.qi_t1})
+      if (ev) (void)hipEventDestroy(ev);
     if (S.stream) (void)hipStreamDestroy(S.stream);
     if (S.h_desc) (void)hipHostFree(S.h_desc);
     if (S.h_tokens) (void)hipHostFree(S.h_tokens);
@@ -332,14 +339,25 @@ void free_pipeline(lshbloom_pipeline *pl) {
   }
 }
 
-// Copy a finished slot's flags to the caller (after its done event).
-int collect(Slot &S) {
+// Copy a finished slot's flags to the caller (after its done event), add its
+// stage times, and report a device status raised by its query-insert (or an
+// earlier call of the handle).
+int collect(lshbloom_pipeline *pl, Slot &S) {
   if (!S.pending) return LSHBLOOM_OK;
   hipError_t e = hipEventSynchronize(S.done);
   if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: wait");
   if (S.n_docs) std::memcpy(S.user_flags, S.h_flags, (size_t)S.n_docs);
   S.pending = false;
-  return LSHBLOOM_OK;
+  float mh = 0.f, qi = 0.f;
+  if (S.n_docs && hipEventElapsedTime(&mh, S.mh_t0, S.mh_t1) == hipSuccess &&
+      hipEventElapsedTime(&qi, S.qi_t0, S.qi_t1) == hipSuccess) {
+    pl->timed_batches += 1;
+    pl->minhash_ms_total += mh;
+    pl->qi_ms_total += qi;
+  }
+  (void)hipGetLastError();
+  std::lock_guard<std::mutex> hk(pl->h->mu);
+  return lbh::check_ready(pl->h);
 }
 
 }  // namespace
@@ -382,6 +400,8 @@ lshbloom_pipeline_t *lshbloom_pipeline_create(lshbloom_t *h, const lshbloom_pipe
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S.copied, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S.mh_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S.done, hipEventDisableTiming);
+    for (hipEvent_t *ev : {&S.mh_t0, &S.mh_t1, &S.qi_t0, &S.qi_t1})
+      if (e == hipSuccess) e = hipEventCreate(ev);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S.h_desc, desc_words(p->max_docs) * 8, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S.h_tokens, p->max_tokens * 4, hipHostMallocDefault);
     if (e == hipSuccess) e = hipHostMalloc((void **)&S.h_flags, p->max_docs, hipHostMallocDefault);
@@ -403,7 +423,7 @@ void lshbloom_pipeline_destroy(lshbloom_pipeline_t *pl) {
   if (!pl) return;
   {
     std::lock_guard<std::mutex> lk(pl->mu);
-    for (Slot &S : pl->slot) (void)collect(S);
+    for (Slot &S : pl->slot) (void)collect(pl, S);
     free_pipeline(pl);
   }
   delete pl;
@@ -417,10 +437,7 @@ int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offse
   }
   std::lock_guard<std::mutex> lk(pl->mu);
   lshbloom *h = pl->h;
-  if (h->poisoned) {
-    set_err("pipeline_submit: handle poisoned by an earlier device error");
-    return LSHBLOOM_EPOISONED;
-  }
+  if (const int crc = lbh::check_ready(h)) return crc;
   if (n_docs < 0 || (uint64_t)n_docs > pl->prm.max_docs || (n_docs > 0 && (!h_offsets || !h_flags))) {
     set_err("pipeline_submit: need 0 <= n_docs <= max_docs and non-null offsets and flags");
     return LSHBLOOM_EINVAL;
@@ -439,7 +456,7 @@ int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offse
   }
   const int64_t ticket = pl->next_ticket;
   Slot &S = pl->slot[ticket % kSlots];
-  int rc = collect(S);  // the slot's previous batch must be done before its buffers are reused
+  int rc = collect(pl, S);  // the slot's previous batch must be done before its buffers are reused
   if (rc) return rc;
   pl->next_ticket++;
   S.ticket = ticket;
@@ -472,32 +489,35 @@ int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offse
     e = hipMemcpyAsync(S.d_desc, S.h_desc, desc_words(n_docs) * 8, hipMemcpyHostToDevice, pl->copy_stream);
   if (e == hipSuccess) e = hipEventRecord(S.copied, pl->copy_stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(S.stream, S.copied, 0);
+  if (e == hipSuccess) e = hipEventRecord(S.mh_t0, S.stream);
   if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: input copy");
   auto g1_body = [&]() -> hipError_t { return enqueue_minhash(pl, S, views, n_docs, bk); };
   e = pl->prm.use_graph ? run_graph(pl, S.stream, S.g1, g1_body) : g1_body();
   if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: MinHash stage");
-  e = hipEventRecord(S.mh_done, S.stream);
+  e = hipEventRecord(S.mh_t1, S.stream);
+  if (e == hipSuccess) e = hipEventRecord(S.mh_done, S.stream);
   if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: event");
 
   {
     std::lock_guard<std::mutex> hk(h->mu);
-    if (h->poisoned) {
-      set_err("pipeline_submit: handle poisoned by an earlier device error");
-      return LSHBLOOM_EPOISONED;
-    }
+    if (const int crc = lbh::check_ready(h)) return crc;
     e = hipStreamWaitEvent(pl->qi_stream, S.mh_done, 0);
     if (e == hipSuccess) e = lbh::begin_ordered(h, pl->qi_stream);
+    if (e == hipSuccess) e = hipEventRecord(S.qi_t0, pl->qi_stream);
     if (e != hipSuccess) return fail_hip(h, e, "pipeline: ordering");
     int qrc = LSHBLOOM_OK;
     auto g2_body = [&]() -> hipError_t {
       qrc = lbh::qi_enqueue(h, S.d_sigs, n_docs, S.d_flags, pl->qi_stream);
-      if (qrc) return hipErrorUnknown;
-      return hipMemcpyAsync(S.h_flags, S.d_flags, (size_t)n_docs, hipMemcpyDeviceToHost, pl->qi_stream);
+      return qrc ? hipErrorUnknown : hipSuccess;
     };
     e = pl->prm.use_graph ? run_graph(pl, pl->qi_stream, S.g2, g2_body) : g2_body();
     if (qrc) return qrc;
     if (e != hipSuccess) return fail_hip(h, e, "pipeline: query-insert stage");
-    e = lbh::end_ordered(h, pl->qi_stream);
+    e = hipEventRecord(S.qi_t1, pl->qi_stream);
+    if (e == hipSuccess) e = lbh::finish_qi(h, pl->qi_stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(S.h_flags, S.d_flags, (size_t)n_docs, hipMemcpyDeviceToHost, pl->qi_stream);
+    if (e == hipSuccess) e = lbh::end_ordered(h, pl->qi_stream);
     if (e == hipSuccess) e = hipEventRecord(S.done, pl->qi_stream);
     if (e != hipSuccess) return fail_hip(h, e, "pipeline: event");
     h->docs_inserted += (uint64_t)n_docs;
@@ -518,7 +538,7 @@ int lshbloom_pipeline_wait(lshbloom_pipeline_t *pl, int64_t ticket) {
   }
   Slot &S = pl->slot[ticket % kSlots];
   if (S.ticket != ticket) return LSHBLOOM_OK;  // an older batch: collected when its slot was reused
-  return collect(S);
+  return collect(pl, S);
 }
 
 int lshbloom_pipeline_poll(lshbloom_pipeline_t *pl, int64_t ticket) {
@@ -536,7 +556,7 @@ int lshbloom_pipeline_poll(lshbloom_pipeline_t *pl, int64_t ticket) {
   const hipError_t q = hipEventQuery(S.done);
   if (q == hipErrorNotReady) return 0;
   if (q != hipSuccess) return fail_hip(nullptr, q, "pipeline_poll: event");
-  const int rc = collect(S);
+  const int rc = collect(pl, S);
   return rc ? rc : 1;
 }
 
@@ -557,6 +577,9 @@ int lshbloom_pipeline_info(const lshbloom_pipeline_t *plc, lshbloom_pipeline_inf
   out->graph_launches = pl->graph_launches;
   out->graph_updates = pl->graph_updates;
   out->graph_instantiations = pl->graph_instantiations;
+  out->timed_batches = pl->timed_batches;
+  out->minhash_ms_total = pl->minhash_ms_total;
+  out->qi_ms_total = pl->qi_ms_total;
   return LSHBLOOM_OK;
 }
 

@@ -17,9 +17,10 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblshbloom.so")
 
-OK, EINVAL, ENOMEM, EHIP, EPOISONED, EIO = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, EPOISONED, EIO, EDEVICE = 0, -1, -2, -3, -4, -5, -6
 QI_AUTO, QI_DIRECT, QI_BINNED = 0, 1, 2
-_CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EPOISONED: "EPOISONED", EIO: "EIO"}
+_CODES = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EHIP: "EHIP", EPOISONED: "EPOISONED", EIO: "EIO",
+          EDEVICE: "EDEVICE"}
 
 
 class LSHBloomError(RuntimeError):
@@ -90,6 +91,9 @@ class PipelineInfo(ctypes.Structure):
         ("graph_launches", ctypes.c_uint64),
         ("graph_updates", ctypes.c_uint64),
         ("graph_instantiations", ctypes.c_uint64),
+        ("timed_batches", ctypes.c_uint64),
+        ("minhash_ms_total", ctypes.c_double),
+        ("qi_ms_total", ctypes.c_double),
     ]
 
 
@@ -102,7 +106,7 @@ EXPORTS = [
     "lshbloom_pipeline_info", "lshbloom_pipeline_destroy",
     "lshbloom_exact_create", "lshbloom_exact_destroy", "lshbloom_exact_query_insert", "lshbloom_exact_stats",
     "lshbloom_query_insert_keys", "lshbloom_minhash61", "lshbloom_band_keys61",
-    "lshbloom_query_insert_noalloc",
+    "lshbloom_query_insert_noalloc", "lshbloom_sync",
 ]
 NOALLOC_MAX_DOCS = 65536
 
@@ -136,6 +140,7 @@ def load(path: str = LIB_PATH):
     L.lshbloom_save.argtypes = [vp, ctypes.c_char_p, vp]
     L.lshbloom_load.argtypes = [vp, ctypes.c_char_p, vp]
     L.lshbloom_info.argtypes = [vp, ctypes.POINTER(Info)]
+    L.lshbloom_sync.argtypes = [vp]
     L.lshbloom_p_band_from_eff.argtypes = [ctypes.c_double, u32]
     L.lshbloom_p_band_from_eff.restype = ctypes.c_double
     L.lshbloom_optimal_bands.argtypes = [ctypes.c_double, u32, ctypes.c_double, ctypes.c_double,
@@ -171,7 +176,8 @@ def load(path: str = LIB_PATH):
     for name in ("lshbloom_minhash", "lshbloom_query_insert", "lshbloom_query_insert_noalloc", "lshbloom_query",
                  "lshbloom_insert",
                  "lshbloom_band_keys", "lshbloom_read_filters", "lshbloom_write_filters",
-                 "lshbloom_count_set_bits", "lshbloom_save", "lshbloom_load", "lshbloom_info", "lshbloom_optimal_bands"):
+                 "lshbloom_count_set_bits", "lshbloom_save", "lshbloom_load", "lshbloom_info", "lshbloom_optimal_bands",
+                 "lshbloom_sync"):
         getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -370,6 +376,10 @@ class LSHBloom:
         di = (1 << 64) - 1 if docs_inserted is None else int(docs_inserted)
         _check(load().lshbloom_write_filters(self._h, ctypes.c_void_p(words.data_ptr()), 0, words.numel() * 8, di,
                                              _stream()))
+
+    def sync(self) -> None:
+        """Wait for the handle's calls; raises EDEVICE if a kernel reported an inconsistency."""
+        _check(load().lshbloom_sync(self._h))
 
     def info(self) -> dict:
         inf = Info()

@@ -76,6 +76,12 @@ def poisson_requests(n_requests: int, docs_per_s: float, size_lo: int, size_hi: 
     return reqs
 
 
+def _report(done: int, total: int, now: float) -> None:
+    import sys
+
+    print(f"[serve] {done}/{total} requests finished after {now:.0f} s", file=sys.stderr, flush=True)
+
+
 class Server:
     """Continuous batching with HBM-budget admission over a Pipeline."""
 
@@ -91,8 +97,10 @@ class Server:
     def batch_bytes(self, docs: int, tokens: int) -> int:
         return tokens * 4 + docs * (self.index.num_perm * 4 + 1)
 
-    def run(self, reqs: list, offsets: torch.Tensor, tokens: torch.Tensor, flags: torch.Tensor) -> ServeResult:
-        """offsets/tokens/flags: host tensors (pinned for DMA) covering every request's documents."""
+    def run(self, reqs: list, offsets: torch.Tensor, tokens: torch.Tensor, flags: torch.Tensor,
+            progress_s: float = 0.0) -> ServeResult:
+        """offsets/tokens/flags: host tensors (pinned for DMA) covering every request's documents.
+        progress_s > 0: print the number of finished requests to stderr that often."""
         off = offsets.numpy()
         lock = threading.Lock()
         inflight = deque()  # (ticket, [requests], bytes)
@@ -123,9 +131,13 @@ class Server:
         th.start()
         waiting = deque()
         nxt = 0
+        last_report = 0.0
         try:
             while True:
                 now = time.perf_counter() - t0
+                if progress_s > 0 and now - last_report >= progress_s:
+                    last_report = now
+                    _report(state["done"], len(reqs), now)
                 while nxt < len(reqs) and reqs[nxt].arrival <= now:
                     waiting.append(reqs[nxt])
                     nxt += 1
@@ -183,10 +195,15 @@ class PlainServer:
         self.pipe = lshbloom.Pipeline(index, max_docs=max_docs, max_tokens=max_tokens, use_graph=use_graph,
                                       autotune=False, n_buckets=1)
 
-    def run(self, reqs: list, offsets: torch.Tensor, tokens: torch.Tensor, flags: torch.Tensor) -> ServeResult:
+    def run(self, reqs: list, offsets: torch.Tensor, tokens: torch.Tensor, flags: torch.Tensor,
+            progress_s: float = 0.0) -> ServeResult:
         t0 = time.perf_counter()
-        for r in reqs:
+        last_report = 0.0
+        for q, r in enumerate(reqs):
             now = time.perf_counter() - t0
+            if progress_s > 0 and now - last_report >= progress_s:
+                last_report = now
+                _report(q, len(reqs), now)
             if r.arrival > now:
                 time.sleep(r.arrival - now)
             t = self.pipe.submit(offsets[r.lo:r.hi + 1], tokens, flags[r.lo:r.hi])
