@@ -564,6 +564,34 @@ int ora_query_insert_keys(ora_index *h, const uint64_t *keys, int64_t n_docs, ui
   return 0;
 }
 
+/* One band's share of the stream (§4.1, §4.2): band j has a Bloom filter of
+   its own that only band j's keys ever reach, so over the stream that filter
+   is itself queried then inserted in document order; hits[i] = 1 iff all k
+   bits of document i's band-j key were set just before document i.  A
+   document's flag is the OR of its bands' hits (§4.2), which is what
+   ora_query_insert computes band by band inside its document loop.  Calls for
+   different bands touch different filters and may run at the same time;
+   docs_inserted is not changed (the caller counts documents once). */
+int ora_query_insert_band(ora_index *h, const uint32_t *sigs, int64_t n_docs, uint32_t band, uint8_t *hits) {
+  if (n_docs < 0 || band >= h->bands) return -1;
+  uint64_t *g = (uint64_t *)malloc(sizeof(uint64_t) * h->k);
+  if (!g) return -1;
+  for (int64_t i = 0; i < n_docs; ++i) {
+    const uint64_t K = ora_band_key(sigs + (uint64_t)i * h->num_perm, band, h->rows, h->salt_m);
+    ora_positions(K, h->salt1, h->salt2, h->m_bits, h->k, g);
+    int all = 1;
+    for (uint32_t l = 0; l < h->k; ++l)
+      if (!ora_test_bit(h, band, g[l])) all = 0;
+    hits[i] = (uint8_t)all;
+    for (uint32_t l = 0; l < h->k; ++l) ora_set_bit(h, band, g[l]);
+  }
+  free(g);
+  return 0;
+}
+
+/* Add n documents to the inserted count (after ora_query_insert_band calls). */
+void ora_count_docs(ora_index *h, uint64_t n) { h->docs_inserted += n; }
+
 /* Accessors for tests. */
 uint64_t ora_m_bits(const ora_index *h) { return h->m_bits; }
 uint32_t ora_k(const ora_index *h) { return h->k; }

@@ -102,6 +102,9 @@ def lib():
         L.ora_docs_inserted.restype = ctypes.c_uint64
         L.ora_coeffs.argtypes = [ctypes.c_void_p, _u64p, _u64p, _u64p]
         L.ora_band_keys.argtypes = [ctypes.c_void_p, _u32p, ctypes.c_int64, _u64p]
+        L.ora_query_insert_band.argtypes = [ctypes.c_void_p, _u32p, ctypes.c_int64, ctypes.c_uint32, _u8p]
+        L.ora_query_insert_band.restype = ctypes.c_int
+        L.ora_count_docs.argtypes = [ctypes.c_void_p, ctypes.c_uint64]
     return _lib
 
 
@@ -268,6 +271,63 @@ class OracleIndex:
         if len(sigs):
             lib().ora_query_insert(self._h, _ptr(sigs, ctypes.c_uint32), len(sigs), _ptr(flags, ctypes.c_uint8))
         return flags
+
+    def query_insert_band(self, sigs: np.ndarray, band: int) -> np.ndarray:
+        """Hits of one band over the stream (that band's filter only)."""
+        sigs = np.ascontiguousarray(sigs, dtype=np.uint32).reshape(-1, self.num_perm)
+        hits = np.zeros(len(sigs), np.uint8)
+        if len(sigs):
+            rc = lib().ora_query_insert_band(self._h, _ptr(sigs, ctypes.c_uint32), len(sigs), band,
+                                             _ptr(hits, ctypes.c_uint8))
+            if rc != 0:
+                raise ValueError("bad band")
+        return hits
+
+    def query_insert_by_band(self, sigs: np.ndarray, threads: int = 1) -> np.ndarray:
+        """query_insert computed one band at a time (bands on up to `threads`
+        host threads, each band's stream sequential); flags = OR of the hits."""
+        from concurrent.futures import ThreadPoolExecutor
+
+        sigs = np.ascontiguousarray(sigs, dtype=np.uint32).reshape(-1, self.num_perm)
+        with ThreadPoolExecutor(max_workers=max(1, int(threads))) as ex:
+            hits = list(ex.map(lambda j: self.query_insert_band(sigs, j), range(self.bands)))
+        lib().ora_count_docs(self._h, len(sigs))
+        flags = np.zeros(len(sigs), np.uint8)
+        for h in hits:
+            flags |= h
+        return flags
+
+    def filters_view(self) -> np.ndarray:
+        """The filter words in place (no copy), shape [bands, words_per_band];
+        valid while the index is open."""
+        n = self.bands * self.words_per_band
+        p = lib().ora_filters(self._h)
+        return np.ctypeslib.as_array(p, shape=(n,)).reshape(self.bands, self.words_per_band)
+
+    def load_file(self, path: str) -> None:
+        """Replace the filters with those of an index file in the documented
+        layout (an 80-byte little-endian header: "LSHBLM01", num_perm, bands,
+        rows, shingle width as u32; expected_n u64; fp_rate f64; seed, m_bits
+        u64; k, 0 u32; docs_inserted, words_per_band u64; then the band-major
+        filter words), after checking that it describes this index."""
+        import struct
+
+        with open(path, "rb") as f:
+            hd = f.read(80)
+            if len(hd) != 80 or hd[:8] != b"LSHBLM01":
+                raise ValueError(f"{path} is not an index file")
+            P, b, r, w, n, p, seed, m, k, _, docs, wpb = struct.unpack("<4IQdQQIIQQ", hd[8:])
+            if (P, b, r, w, m, k, wpb) != (self.num_perm, self.bands, self.rows, self.w, self.m_bits, self.k,
+                                           self.words_per_band):
+                raise ValueError(f"{path} holds an index of other parameters")
+            view = self.filters_view().reshape(-1)
+            step = 1 << 24
+            for a in range(0, view.size, step):
+                chunk = np.frombuffer(f.read(8 * min(step, view.size - a)), dtype="<u8")
+                if chunk.size != min(step, view.size - a):
+                    raise ValueError(f"{path} is shorter than its header says")
+                view[a:a + chunk.size] = chunk
+        lib().ora_count_docs(self._h, docs - self.docs_inserted)
 
     def query(self, sigs: np.ndarray) -> np.ndarray:
         sigs = np.ascontiguousarray(sigs, dtype=np.uint32).reshape(-1, self.num_perm)

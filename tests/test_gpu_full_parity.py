@@ -1,0 +1,139 @@
+"""Element-by-element GPU parity at production geometry.
+
+* The 10M-document batched configuration: two 1M-document batches of its
+  recipe through the launch configuration the benchmark times (the pipeline:
+  length buckets, hipGraph replay, autotuner, one binned query-insert chunk
+  per batch, 2^15-bit dense bins, 458 pass-1 buckets per band).  Every
+  signature, every flag and every word of the 15.3 GB of filters is compared
+  with the oracle.
+* The filter-scale stream at its per-band shape: 4 bands of 5.99 GB each
+  (n = 1e9 at a per-band rate of 1e-10, the share of one GPU of eight under
+  band sharding), three 1M-signature chunks (2^18-bit sparse bins, 715
+  pass-1 buckets per band).  Every flag and every filter word is compared
+  with the oracle.
+
+The oracle replays the stream one band at a time on the host's cores (each
+band's filter only ever sees that band's keys, and a document's flag is the
+OR of its bands' hits, Sections 4.1-4.2); its MinHash runs over host threads
+with each document the sequential definition.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2411_04257_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _threads():
+    n = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        n = min(n, int(os.environ["OMP_NUM_THREADS"]))
+    return max(1, min(n, 32))
+
+
+def _bench_index(gpu, wl, bands=None):
+    # the benchmark's index configuration: one binned chunk per batch
+    b = wl.bands if bands is None else bands
+    return gpu.LSHBloom(wl.num_perm, b, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed,
+                        chunk_docs=wl.batch, workspace_budget=24 * wl.batch * b * 40 + (64 << 20))
+
+
+def _band_words(gpu, g, band):
+    out = np.empty(g.words_per_band, np.uint64)
+    rc = gpu.load().lshbloom_read_filters(g._h, ctypes.c_void_p(out.ctypes.data), band * g.words_per_band * 8,
+                                          g.words_per_band * 8, None)
+    assert rc == 0, gpu.last_error()
+    return out
+
+
+def _compare_filters(gpu, g, o):
+    want = o.filters_view()
+    for j in range(g.bands):
+        got = _band_words(gpu, g, j)
+        if not np.array_equal(got, want[j]):
+            bad = np.flatnonzero(got != want[j])
+            raise AssertionError(f"band {j}: {len(bad)} filter words differ, first at word {bad[0]}: "
+                                 f"{int(got[bad[0]]):#x} vs {int(want[j][bad[0]]):#x}")
+
+
+def test_c3_batches_element_wise(gpu):
+    wl = synth.WORKLOADS["c3"]
+    B, n_batches = wl.batch, 2
+    print(f"c3 element-wise: {n_batches} x {B} documents, pipeline launch configuration", flush=True)
+    corpus = synth.make_corpus(wl, device="cuda", n_docs=B * n_batches)
+    h_off = torch.empty(corpus.offsets.numel(), dtype=torch.int64, pin_memory=True)
+    h_off.copy_(corpus.offsets)
+    h_tok = torch.empty(corpus.tokens.numel(), dtype=torch.int32, pin_memory=True)
+    h_tok.copy_(corpus.tokens)
+    lengths = torch.diff(corpus.offsets).cpu().numpy()
+    max_tok = int(max(lengths[b * B:(b + 1) * B].sum() for b in range(n_batches)))
+
+    g = _bench_index(gpu, wl)
+    assert g.info()["binned_chunk_docs"] >= B and g.info()["filter_bytes"] == 15_336_093_440
+    pl = gpu.Pipeline(g, max_docs=B, max_tokens=max_tok, use_graph=True, autotune=True)
+    flags = torch.zeros((n_batches, B), dtype=torch.uint8).pin_memory()
+    offs = [h_off[b * B:(b + 1) * B + 1].clone() for b in range(n_batches)]
+    tickets = [pl.submit(offs[b], h_tok, flags[b]) for b in range(n_batches)]
+    for t in tickets:
+        pl.wait(t)
+    pl.close()
+    g.sync()
+    # the same documents' signatures through lshbloom_minhash (stateless)
+    sigs = g.minhash(corpus.offsets, corpus.tokens).cpu().numpy().view(np.uint32)
+    del corpus
+    torch.cuda.empty_cache()
+
+    o = oracle.OracleIndex(wl.num_perm, wl.bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
+    assert (o.m_bits, o.k) == (g.m_bits, g.k)
+    off = h_off.numpy()
+    tok = h_tok.numpy().view(np.uint32)
+    want_sigs = o.minhash_threads(off, tok, _threads())
+    bad = np.flatnonzero((sigs != want_sigs).any(axis=1))
+    assert len(bad) == 0, f"{len(bad)} signatures differ, first document {bad[:5]}"
+    want = o.query_insert_by_band(want_sigs, _threads())
+    got = flags.numpy().reshape(-1)
+    bad = np.flatnonzero(got != want)
+    assert len(bad) == 0, f"{len(bad)} flags differ, first documents {bad[:5]}"
+    assert 0.1 < want.mean() < 0.4
+    _compare_filters(gpu, g, o)
+    o.close()
+    g.close()
+
+
+def test_c4_band_shard_element_wise(gpu):
+    wl = synth.WORKLOADS["c4"]
+    bands, B, n_batches = 4, wl.batch, 3
+    ex = wl.extra
+    print(f"c4 element-wise: {bands}-band shard, {n_batches} x {B} signatures", flush=True)
+    g = _bench_index(gpu, wl, bands=bands)
+    assert g.info()["filter_bytes"] == 4 * 5_990_661_488 and g.k == 33
+    sig_batches, flags = [], []
+    for t in range(n_batches):
+        s = synth.signature_batch(t * B, B, wl.num_perm, bands, wl.rows, B, ex["repeat_frac"], ex["in_batch_frac"],
+                                  wl.corpus_seed, device="cuda")
+        flags.append(g.query_insert(s).cpu().numpy())
+        sig_batches.append(s.cpu().numpy().view(np.uint32))
+        del s
+    g.sync()
+    flags = np.concatenate(flags)
+    sigs = np.concatenate(sig_batches)
+    del sig_batches
+    o = oracle.OracleIndex(wl.num_perm, bands, wl.rows, wl.expected_n, wl.fp_rate, wl.index_seed)
+    assert (o.m_bits, o.k) == (g.m_bits, g.k)
+    want = o.query_insert_by_band(sigs, _threads())
+    bad = np.flatnonzero(flags != want)
+    assert len(bad) == 0, f"{len(bad)} flags differ, first signatures {bad[:5]}"
+    rep, _ = synth.signature_repeat_info(0, n_batches * B, bands, B, ex["repeat_frac"], ex["in_batch_frac"],
+                                         wl.corpus_seed)
+    rep = rep.numpy()
+    assert rep.mean() > 0.25 and want[rep].all()
+    _compare_filters(gpu, g, o)
+    o.close()
+    g.close()

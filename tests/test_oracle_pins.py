@@ -598,3 +598,71 @@ def test_wide_pipeline_flags_repeats():
     tok = np.concatenate(docs)
     flags = idx.query_insert_keys(idx.band_keys61(idx.minhash61(off, tok)))
     assert flags[:200].sum() == 0 and flags[200:].all()
+
+
+@pytest.mark.parametrize("bands,rows,n,p", [(16, 8, 3000, 1e-3), (3, 5, 500, 0.2), (32, 8, 2000, 1e-8)])
+def test_query_insert_by_band_equals_query_insert(bands, rows, n, p):
+    """Each band has a filter of its own (Section 4.1) and a document is a
+    duplicate when any band reports it (Section 4.2): the stream run one band
+    at a time, with the bands' hits ORed, gives the flags and filters of the
+    document-at-a-time run, on a stream with in-batch repeats."""
+    from paper_2411_04257_amd import synth
+
+    P = bands * rows + 3
+    s = synth.signature_batch(0, n, P, bands, rows, n, 0.3, 0.5, 23).numpy().view(np.uint32)
+    i1 = oracle.OracleIndex(P, bands, rows, n, p, seed=9)
+    i2 = oracle.OracleIndex(P, bands, rows, n, p, seed=9)
+    f1 = i1.query_insert(s)
+    f2 = i2.query_insert_by_band(s, threads=4)
+    assert f1.tolist() == f2.tolist() and 0 < f1.sum() < n
+    assert (i1.filters() == i2.filters_view()).all()
+    assert i2.docs_inserted == n
+
+
+def test_query_insert_band_against_set_model():
+    """Brute force on a tiny filter: band j's hit for document i is 1 iff
+    every one of its k positions was a position of an earlier document's
+    band-j key (Section 2.4: a Bloom filter answers membership of the set of
+    bits inserted so far), computed with Python sets."""
+    rng = np.random.default_rng(77)
+    P, bands, rows = 12, 3, 4
+    idx = oracle.OracleIndex(P, bands, rows, 40, 0.3, seed=5)
+    base = rng.integers(0, 2**32, (60, P), dtype=np.uint64).astype(np.uint32)
+    base[30:] = base[rng.integers(0, 30, 30)]  # repeats of earlier documents
+    base[45:, :4] = rng.integers(0, 2**32, (15, 4), dtype=np.uint64).astype(np.uint32)  # band 0 fresh
+    salt_m, s1, s2 = idx.coeffs()[2]
+    for j in range(bands):
+        seen = set()
+        want = []
+        for i in range(len(base)):
+            key = oracle.band_key(base[i], j, rows, salt_m)
+            pos = set(int(g) for g in oracle.positions(key, s1, s2, idx.m_bits, idx.k))
+            want.append(int(pos <= seen))
+            seen |= pos
+        assert idx.query_insert_band(base, j).tolist() == want
+    assert sum(want) >= 15
+
+
+def test_oracle_reads_the_documented_index_file(tmp_path):
+    """The oracle's reader of the index file layout (a header that must
+    describe this index, then the band-major words), on a file written here
+    byte by byte from that layout."""
+    import struct
+
+    o = oracle.OracleIndex(16, 2, 8, 1000, 1e-3, seed=4)
+    rng = np.random.default_rng(8)
+    words = rng.integers(0, 2**63, 2 * o.words_per_band, dtype=np.uint64)
+    hd = b"LSHBLM01" + struct.pack("<4IQdQQIIQQ", 16, 2, 8, 5, 1000, 1e-3, 4, o.m_bits, o.k, 0, 123,
+                                    o.words_per_band)
+    path = tmp_path / "idx.bin"
+    path.write_bytes(hd + words.astype("<u8").tobytes())
+    o.load_file(str(path))
+    assert (o.filters().reshape(-1) == words).all() and o.docs_inserted == 123
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(hd.replace(struct.pack("<I", 16), struct.pack("<I", 17), 1) + words.tobytes())
+    with pytest.raises(ValueError):
+        o.load_file(str(bad))
+    short = tmp_path / "short.bin"
+    short.write_bytes(hd + words.tobytes()[:-8])
+    with pytest.raises(ValueError):
+        o.load_file(str(short))
