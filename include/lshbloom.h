@@ -339,14 +339,14 @@ void lshbloom_pipeline_destroy(lshbloom_pipeline_t *pl);
 
 /* ---- Exact MinHashLSH band index (the comparison baseline) ----------------
  *
- * The traditional index that LSHBloom replaces (Section 2, "MinHashLSH for
- * Text Deduplication"; Section 3): per band, a hash table keyed by the band's
+ * The traditional index that LSHBloom replaces (Section 2.3, "MinHashLSH
+ * for Text Deduplication"; Section 4): per band, a hash table keyed by the band's
  * r signature values, compared exactly.  Document i is flagged iff, for some
  * band j, its r values of band j equal those of an earlier document (of an
  * earlier call, or 0..i-1 of this call); every document is then inserted.
  * On the same stream LSHBloom's flags contain these flags (equal band values
  * give equal band keys); the difference is the Bloom filters' false positives
- * and band-key collisions (Section 3.2).  Device memory, allocated by create:
+ * and band-key collisions (Section 4.3, Eq. 3).  Device memory, allocated by create:
  * per band 2^ceil(log2(2 capacity)) slots of 12 + 4 r bytes. */
 typedef struct lshbloom_exact lshbloom_exact_t;
 

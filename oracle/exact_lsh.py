@@ -1,7 +1,7 @@
 """Exact MinHashLSH band index, CPU reference (test infrastructure only).
 
-MinHashLSH as the paper describes it (Section 2, "MinHashLSH for Text
-Deduplication"; Section 3, first paragraph of the method): the signature
+MinHashLSH as the paper describes it (Section 2.3, "MinHashLSH for Text
+Deduplication"; Section 4, opening paragraphs of the method): the signature
 matrix is cut into b bands of r rows, and two documents whose signatures are
 identical over all r rows of some band are a candidate pair, taken here as a
 duplicate.  The traditional index keeps, per band, a hash map keyed by the
@@ -9,7 +9,7 @@ band's r values.  In a stream, document i is flagged iff some band of its
 signature equals the same band of an earlier document's signature; every
 document is inserted after its query (flagged or not), the same order the
 LSHBloom reference follows, so that the two indexes answer the same question
-and differ only by the Bloom filters' false positives (Section 3.2).
+and differ only by the Bloom filters' false positives (Section 4.3, Eq. 3).
 
 Plain Python dictionaries keyed by the band's bytes; no hashing of the band
 values of our own, no batching: one document after the other.  Only the

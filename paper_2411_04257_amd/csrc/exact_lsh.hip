@@ -1,5 +1,5 @@
 // Exact MinHashLSH band index: the traditional index LSHBloom replaces
-// (Section 2, "MinHashLSH for Text Deduplication"; Section 3), kept on the
+// (Section 2.3, "MinHashLSH for Text Deduplication"; Section 4), kept on the
 // device as the comparison baseline.
 //
 // Per band an open-addressing table of 2^t slots (load <= 1/2 at capacity):

@@ -471,7 +471,7 @@ def test_exact_oracle_without_repeats_flags_nothing():
 
 def test_exact_oracle_contained_in_bloom_oracle():
     """Exact band match implies the same band key and so the same Bloom
-    bits: LSHBloom's flags contain MinHashLSH's (Section 3.2); the excess
+    bits: LSHBloom's flags contain MinHashLSH's (Section 4.3, Eq. 3); the excess
     stays within the Bloom false-positive budget."""
     from oracle.exact_lsh import ExactLSHOracle
 
