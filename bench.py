@@ -447,7 +447,7 @@ def run_batched(args, wl, torch, np, lshbloom, synth, dev):
                          f"kernels, mean over the {nb} timed batches")
     mh_roof = minhash_roofline(wl, shingles, [mh_ms_mean] * args.steps,
                                "k_minhash, one launch per length bucket (incl. the signature pre-fill)")
-    mh_roof["timing"] = "HIP events on the pipeline's slot streams around each batch's MinHash stage"
+    mh_roof["timing"] = "HIP events on the pipeline's MinHash stream around each batch's MinHash stage"
     dominant, other = (qi_roof, mh_roof) if qi_ms_mean >= mh_ms_mean else (mh_roof, qi_roof)
     same = bool(torch.equal(batched_flags, pflags[args.warmup:])) and bool(torch.equal(batched_flags, dev_flags))
     res = {

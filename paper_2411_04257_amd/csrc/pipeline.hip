@@ -9,8 +9,8 @@
 //           device a host-to-device copy runs as a blit kernel, so copies
 //           of two slots started together would share the link and finish
 //           together, and neither batch's MinHash could start early);
-//   slot stream (graph G1): after its batch's copy, signature pre-fill and
-//           one MinHash launch per non-empty bucket;
+//   MinHash stream (graph G1 of the batch's slot): after its batch's copy,
+//           signature pre-fill and one MinHash launch per non-empty bucket;
 //   query-insert stream (graph G2): after G1 of this batch and after every
 //           earlier filter call of the handle, the in-order query-insert and
 //           the D2H copy of the flags.
@@ -40,9 +40,8 @@ constexpr int kSlots = 2;
 constexpr uint32_t kMaxBuckets = 4;
 
 struct Slot {
-  hipStream_t stream = nullptr;
   hipEvent_t copied = nullptr, mh_done = nullptr, done = nullptr;
-  // timing events around the batch's MinHash stage (slot stream) and its
+  // timing events around the batch's MinHash stage (MinHash stream) and its
   // query-insert kernels (query-insert stream)
   hipEvent_t mh_t0 = nullptr, mh_t1 = nullptr, qi_t0 = nullptr, qi_t1 = nullptr;
   int64_t *h_desc = nullptr;     // pinned bucket descriptors
@@ -71,7 +70,13 @@ struct lshbloom_pipeline {
   lshbloom_pipeline_params_t prm{};
   Buckets bk;
   int cus = 256;
+  // One stream per stage: the MinHash launches of every batch (one after the
+  // other: each fills the device), the query-inserts in submission order, and
+  // the host-to-device copies.  With the process's null stream that is four
+  // streams, so under the runtime's default of four hardware queues each gets
+  // a queue of its own (two streams that share a queue run one after the other).
   hipStream_t qi_stream = nullptr;
+  hipStream_t mh_stream = nullptr;
   hipStream_t copy_stream = nullptr;
   Slot slot[kSlots];
   int64_t next_ticket = 0;
@@ -137,7 +142,7 @@ void build_buckets(const Buckets &bk, const int64_t *off, int64_t n, int64_t *de
 hipError_t enqueue_minhash(lshbloom_pipeline *pl, Slot &S, const BucketView *views, int64_t n,
                            const Buckets &bk) {
   lshbloom *h = pl->h;
-  hipError_t e = lb::launch_fill_u32(S.d_sigs, (uint64_t)n * h->prm.num_perm, 0xFFFFFFFFu, S.stream);
+  hipError_t e = lb::launch_fill_u32(S.d_sigs, (uint64_t)n * h->prm.num_perm, 0xFFFFFFFFu, pl->mh_stream);
   if (e != hipSuccess) return e;
   for (uint32_t b = 0; b < bk.n; ++b) {
     if (views[b].count == 0) continue;
@@ -153,7 +158,7 @@ hipError_t enqueue_minhash(lshbloom_pipeline *pl, Slot &S, const BucketView *vie
                                  : lb::minhash_waves_for_tokens(pl->cus, (uint64_t)views[b].tokens);
     a.tok_shift = S.d_desc + views[b].shift;
     a.row_ids = S.d_desc + views[b].row;
-    e = lb::launch_minhash(a, S.stream);
+    e = lb::launch_minhash(a, pl->mh_stream);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -282,12 +287,12 @@ int autotune(lshbloom_pipeline *pl, Slot &S, const int64_t *off, int64_t n) {
   BucketView views[kMaxBuckets];
   for (const Buckets &b : cands) {
     build_buckets(b, off, n, S.h_desc, views);
-    hipError_t e = hipMemcpyAsync(S.d_desc, S.h_desc, desc_words(n) * 8, hipMemcpyHostToDevice, S.stream);
+    hipError_t e = hipMemcpyAsync(S.d_desc, S.h_desc, desc_words(n) * 8, hipMemcpyHostToDevice, pl->mh_stream);
     float ms = 0.f;
     for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-      e = hipEventRecord(e0, S.stream);
+      e = hipEventRecord(e0, pl->mh_stream);
       if (e == hipSuccess) e = enqueue_minhash(pl, S, views, n, b);
-      if (e == hipSuccess) e = hipEventRecord(e1, S.stream);
+      if (e == hipSuccess) e = hipEventRecord(e1, pl->mh_stream);
       if (e == hipSuccess) e = hipEventSynchronize(e1);
       if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     }
@@ -311,8 +316,8 @@ int autotune(lshbloom_pipeline *pl, Slot &S, const int64_t *off, int64_t n) {
 }
 
 void free_pipeline(lshbloom_pipeline *pl) {
+  if (pl->mh_stream) (void)hipStreamSynchronize(pl->mh_stream);
   for (Slot &S : pl->slot) {
-    if (S.stream) (void)hipStreamSynchronize(S.stream);
     if (S.g1) (void)hipGraphExecDestroy(S.g1);
     if (S.g2) (void)hipGraphExecDestroy(S.g2);
     if (S.copied) (void)hipEventDestroy(S.copied);
@@ -320,7 +325,6 @@ void free_pipeline(lshbloom_pipeline *pl) {
     if (S.done) (void)hipEventDestroy(S.done);
     for (hipEvent_t ev : {S.mh_t0, S.mh_t1, S.qi_t0, S.qi_t1})
       if (ev) (void)hipEventDestroy(ev);
-    if (S.stream) (void)hipStreamDestroy(S.stream);
     if (S.h_desc) (void)hipHostFree(S.h_desc);
     if (S.h_tokens) (void)hipHostFree(S.h_tokens);
     if (S.h_flags) (void)hipHostFree(S.h_flags);
@@ -337,6 +341,7 @@ void free_pipeline(lshbloom_pipeline *pl) {
     (void)hipStreamSynchronize(pl->copy_stream);
     (void)hipStreamDestroy(pl->copy_stream);
   }
+  if (pl->mh_stream) (void)hipStreamDestroy(pl->mh_stream);
 }
 
 // Copy a finished slot's flags to the caller (after its done event), add its
@@ -392,12 +397,12 @@ lshbloom_pipeline_t *lshbloom_pipeline_create(lshbloom_t *h, const lshbloom_pipe
   hipError_t e = hipGetDeviceProperties(&dp, h->device);
   if (e == hipSuccess) pl->cus = dp.multiProcessorCount;
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->qi_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->mh_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->copy_stream, hipStreamNonBlocking);
   const uint64_t P = h->prm.num_perm;
   for (int q = 0; q < kSlots && e == hipSuccess; ++q) {
     Slot &S = pl->slot[q];
-    e = hipStreamCreateWithFlags(&S.stream, hipStreamNonBlocking);
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&S.copied, hipEventDisableTiming);
+    e = hipEventCreateWithFlags(&S.copied, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S.mh_done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&S.done, hipEventDisableTiming);
     for (hipEvent_t *ev : {&S.mh_t0, &S.mh_t1, &S.qi_t0, &S.qi_t1})
@@ -472,12 +477,12 @@ int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offse
   }
   hipError_t e = hipSuccess;
   if (!pl->tuned) {
-    e = hipMemcpyAsync(S.d_tokens, src, (size_t)n_tok * 4, hipMemcpyHostToDevice, S.stream);
+    e = hipMemcpyAsync(S.d_tokens, src, (size_t)n_tok * 4, hipMemcpyHostToDevice, pl->mh_stream);
     if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: token copy");
     rc = autotune(pl, S, h_offsets, n_docs);
     if (rc) return rc;
     // the slot's device buffers are rewritten on the copy stream below
-    if ((e = hipStreamSynchronize(S.stream)) != hipSuccess) return fail_hip(nullptr, e, "pipeline: tuning");
+    if ((e = hipStreamSynchronize(pl->mh_stream)) != hipSuccess) return fail_hip(nullptr, e, "pipeline: tuning");
   }
   BucketView views[kMaxBuckets];
   build_buckets(pl->bk, h_offsets, n_docs, S.h_desc, views);
@@ -488,14 +493,14 @@ int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offse
   if (e == hipSuccess)
     e = hipMemcpyAsync(S.d_desc, S.h_desc, desc_words(n_docs) * 8, hipMemcpyHostToDevice, pl->copy_stream);
   if (e == hipSuccess) e = hipEventRecord(S.copied, pl->copy_stream);
-  if (e == hipSuccess) e = hipStreamWaitEvent(S.stream, S.copied, 0);
-  if (e == hipSuccess) e = hipEventRecord(S.mh_t0, S.stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(pl->mh_stream, S.copied, 0);
+  if (e == hipSuccess) e = hipEventRecord(S.mh_t0, pl->mh_stream);
   if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: input copy");
   auto g1_body = [&]() -> hipError_t { return enqueue_minhash(pl, S, views, n_docs, bk); };
-  e = pl->prm.use_graph ? run_graph(pl, S.stream, S.g1, g1_body) : g1_body();
+  e = pl->prm.use_graph ? run_graph(pl, pl->mh_stream, S.g1, g1_body) : g1_body();
   if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: MinHash stage");
-  e = hipEventRecord(S.mh_t1, S.stream);
-  if (e == hipSuccess) e = hipEventRecord(S.mh_done, S.stream);
+  e = hipEventRecord(S.mh_t1, pl->mh_stream);
+  if (e == hipSuccess) e = hipEventRecord(S.mh_done, pl->mh_stream);
   if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: event");
 
   {

@@ -8,8 +8,11 @@ namespace lb {
 
 // Documents per pass-1 block (a power of two: a block's probe slots are
 // enumerated l-major, slot = l * kTileDocs + document).
-constexpr uint32_t kTileDocs = 1024;
-constexpr uint32_t kTileLog = 10;
+#ifndef LB_TILE_LOG
+#define LB_TILE_LOG 10
+#endif
+constexpr uint32_t kTileLog = LB_TILE_LOG;
+constexpr uint32_t kTileDocs = 1u << kTileLog;
 // Largest chunk the 64-bit record format holds: document index in 23 bits.
 constexpr uint64_t kBinnedMaxDocs = (1ull << 23) - 1;
 // Records per chunk must stay below 2^31 (32-bit record offsets and table caps).

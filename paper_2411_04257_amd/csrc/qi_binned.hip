@@ -182,8 +182,11 @@ __global__ __launch_bounds__(256) void k_bq_keys_in(BinnedLaunch A) {
 // counts of the block.  k_bq_scatter1 (1024 threads, one block per compute
 // unit): the records, staged in LDS by bucket in sub-tiles of 16,384 so that
 // each bucket's share leaves as one run, written at counts-derived offsets.
-constexpr uint32_t kT1 = 1024;
-constexpr uint32_t kPer1 = 16;
+#ifndef LB_PER1
+#define LB_PER1 16
+#endif
+constexpr uint32_t kT1 = kTileDocs;
+constexpr uint32_t kPer1 = LB_PER1;
 constexpr uint32_t kSub1 = kT1 * kPer1;
 
 __global__ __launch_bounds__(256) void k_bq_count1(BinnedLaunch A) {
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(256) void k_bq_count1(BinnedLaunch A) {
   for (uint32_t f = threadIdx.x; f < F1; f += kThreads) A.counts[row + (uint64_t)f * G.n_tiles] = hist[f];
 }
 
-__global__ __launch_bounds__(1024) void k_bq_scatter1(BinnedLaunch A) {
+__global__ __launch_bounds__(kT1) void k_bq_scatter1(BinnedLaunch A) {
   extern __shared__ __align__(16) uint8_t smem[];
   const BinnedGeometry &G = A.G;
   const uint32_t F1 = G.buckets_per_band;
@@ -300,11 +303,17 @@ __global__ __launch_bounds__(256) void k_bq_scan_buckets(BinnedLaunch A) {
 // count its bins, publish their record ranges, and split the bucket into
 // bins through LDS-staged sub-tiles of 16,384 records, so that each bin's
 // share of a sub-tile leaves as one contiguous run.
-constexpr uint32_t kT2 = 1024;
-constexpr uint32_t kPer2 = 16;
+#ifndef LB_T2
+#define LB_T2 1024
+#endif
+#ifndef LB_PER2
+#define LB_PER2 16
+#endif
+constexpr uint32_t kT2 = LB_T2;
+constexpr uint32_t kPer2 = LB_PER2;
 constexpr uint32_t kSub2 = kT2 * kPer2;
 
-__global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
+__global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
   extern __shared__ __align__(16) uint8_t smem[];
   const BinnedGeometry &G = A.G;
   const uint32_t F2 = G.bins_per_bucket;
@@ -402,7 +411,10 @@ __global__ __launch_bounds__(1024) void k_bq_part2(BinnedLaunch A) {
 // the least document.
 constexpr uint32_t kWCap = 320;               // records per bin on the wave path
 constexpr uint32_t kWPer = kWCap / 64;        // records per lane
-constexpr uint32_t kWTab = 2 * kWCap;         // bit / word table slots
+#ifndef LB_BIN_TAB
+#define LB_BIN_TAB (2 * kWCap)
+#endif
+constexpr uint32_t kWTab = LB_BIN_TAB;        // bit / word table slots (at most 2 per record)
 constexpr uint32_t kWRegion = 512;            // direct mode: the bin's words (bin_bits <= 15)
 constexpr uint32_t kMulti = 0x80000000u;
 
@@ -489,7 +501,10 @@ __device__ void bin_global(const BinnedLaunch &A, uint32_t j, uint64_t bin, uint
 }
 
 template <bool DIRECT>
-__global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
+#ifndef LB_BIN_WAVES
+#define LB_BIN_WAVES 1
+#endif
+__global__ __launch_bounds__(64, LB_BIN_WAVES) void k_bq_bin(BinnedLaunch A) {
   // tmin[slot]: 0 if the bit was set before the chunk, else 1 + the least
   // document probing it (so one atomicMin serves both), kNoFs before any.
   __shared__ __align__(16) uint32_t tkey[kWTab];
@@ -546,7 +561,7 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     const uint64_t lbin = bin - (uint64_t)j * G.bins_per_band;
     const uint64_t b0 = lbin << G.bin_bits;  // first bit of the bin (a multiple of 64)
     uint64_t *F = A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6);
-    const uint32_t cap = 2 * nr;
+    const uint32_t cap = min(2 * nr, kWTab);
     const uint32_t W = (uint32_t)min((uint64_t)1 << (G.bin_bits - 6), A.words_per_band - (b0 >> 6));
     // a full bin (every bin but the last of a band) is written back whole
     const bool full = W == (1u << (G.bin_bits - 6));
@@ -554,13 +569,13 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
     // the next bin's records
     if (DIRECT) {
       // both tables whole, 16 bytes per store
-      static_assert(kWTab % 4 == 0 && kWTab / 4 <= 192, "three stores per lane");
+      static_assert(kWTab % 4 == 0 && kWTab / 4 <= 192 && kWTab >= kWCap, "three stores per lane");
       uint4 *k4 = reinterpret_cast<uint4 *>(tkey), *m4 = reinterpret_cast<uint4 *>(tmin);
       const uint4 z = make_uint4(0u, 0u, 0u, 0u), nf = make_uint4(kNoFs, kNoFs, kNoFs, kNoFs);
 #pragma unroll
       for (uint32_t t = 0; t < 3; ++t) {
         const uint32_t q = t * 64 + lane;
-        if (t < 2 || q < kWTab / 4) {
+        if ((t + 1) * 64 <= kWTab / 4 || q < kWTab / 4) {
           k4[q] = z;
           m4[q] = nf;
         }
@@ -656,7 +671,7 @@ __global__ __launch_bounds__(64) void k_bq_bin(BinnedLaunch A) {
           slot[u] = (slot[u] + 1 == cap) ? 0 : slot[u] + 1;
       }
     }
-    if (pend) atomicOr(A.status, 4u);  // cannot happen: cap >= 2 x distinct bits
+    if (pend) atomicOr(A.status, 4u);  // cannot happen: cap >= distinct bits
     wave_sync();
     // least document (+1) probing each clear bit, 0 for bits set before the
     // chunk (every record of a bit sees the same state)
