@@ -76,12 +76,14 @@ def qi_traffic(workload: str):
     return None if r is None else r[0] + r[1]
 
 
-def minhash_counts(ppl: int, w: int):
-    """VALU lane-operations per shingle hash and per evaluation of the
-    k_minhash<PPL, w> instance, from its SQ_INSTS_VALU counter runs in
-    profiles/k_minhash_valu_counters.md for the kernel version built here."""
+def minhash_ops_per_shingle(workload: str, ppl: int, w: int):
+    """VALU lane-operations the k_minhash<PPL, w> instance issues per shingle
+    on `workload`'s documents (SQ_INSTS_VALU x 64 / shingles, from the counter
+    runs in profiles/k_minhash_valu_counters.md) for the kernel version built
+    here; None otherwise."""
     rows = profile_rows("k_minhash_valu_counters.md", source_tag("kernels.hip", "device_math.h"))
-    return rows.get(f"ppl{ppl}_w{w}")
+    r = rows.get(f"{workload}_ppl{ppl}_w{w}")
+    return None if r is None else r[0]
 
 
 def minhash_ppl(num_perm: int) -> int:
@@ -224,26 +226,23 @@ def qi_roofline(wl, args, batch, probes, new_bits, qi_ms, filter_bytes, traffic_
     return roof
 
 
-def minhash_roofline(wl, shingles, mh_ms, kernel):
+def minhash_roofline(wl, workload, shingles, mh_ms, kernel):
     """Roofline object of the MinHash stage.  `shingle_perm_per_s` is the
-    algorithmic rate; `achieved` prices each shingle hash and each evaluation
-    at the VALU lane-operations its k_minhash instance issues per unit
-    (counted by SQ_INSTS_VALU for this kernel version), so `frac` is the
-    stage's share of the INT32 VALU issue peak (None when the instance has
-    no counter profile)."""
+    algorithmic rate (shingle x permutation evaluations per second).
+    `achieved` prices each shingle at the VALU lane-operations its k_minhash
+    instance issues per shingle on this workload (SQ_INSTS_VALU of this
+    kernel version), so `frac` is the stage's share of the INT32 VALU issue
+    peak (None when the instance has no counter profile)."""
     import numpy as np
 
     per_s = float(np.mean([sh * wl.num_perm / (t * 1e-3) for sh, t in zip(shingles, mh_ms)]))
-    counts = minhash_counts(minhash_ppl(wl.num_perm), 5)
+    ops = minhash_ops_per_shingle(workload, minhash_ppl(wl.num_perm), 5)
     roof = {"bound": "alu", "kernel": kernel, "achieved": None, "peak": INT32_VALU_PEAK / 1e12,
             "unit": "TOPS (int32 VALU lane-ops/s)", "frac": None, "traffic": None,
             "shingle_perm_per_s": per_s, "stage_ms_mean": float(np.mean(mh_ms))}
-    if counts:
-        ops_hash, ops_eval = counts[0], counts[1]
-        ach = float(np.mean([sh * (ops_hash + wl.num_perm * ops_eval) / (t * 1e-3)
-                             for sh, t in zip(shingles, mh_ms)]))
-        roof.update(achieved=ach / 1e12, frac=ach / INT32_VALU_PEAK,
-                    ops_per_shingle_hash=ops_hash, ops_per_evaluation=ops_eval)
+    if ops:
+        ach = float(np.mean([sh * ops / (t * 1e-3) for sh, t in zip(shingles, mh_ms)]))
+        roof.update(achieved=ach / 1e12, frac=ach / INT32_VALU_PEAK, ops_per_shingle=ops)
     return roof
 
 
@@ -334,7 +333,7 @@ def run_corpus(args, wl, torch, np, lshbloom, synth, dev):
     shingles = [shingle_count(lengths[b * B:(b + 1) * B]) for b in timed]
     tokens = [int(lengths[b * B:(b + 1) * B].sum()) for b in timed]
     probes = B * wl.bands * r["k"]
-    minhash_roof = minhash_roofline(wl, shingles, r["mh_ms"], "k_minhash (incl. its 0xFFFFFFFF pre-fill)")
+    minhash_roof = minhash_roofline(wl, args.workload, shingles, r["mh_ms"], "k_minhash (incl. its 0xFFFFFFFF pre-fill)")
     qi_roof = qi_roofline(wl, args, B, probes, r["new_bits"], r["qi_ms"], r["filter_bytes"],
                           None if args.wide else args.workload)
     if args.wide:
@@ -445,7 +444,7 @@ def run_batched(args, wl, torch, np, lshbloom, synth, dev):
     qi_roof = qi_roofline(wl, args, B, probes, new_bits, [qi_ms_mean] * args.steps, filter_bytes, args.workload)
     qi_roof["timing"] = ("HIP events on the pipeline's query-insert stream around each batch's query-insert "
                          f"kernels, mean over the {nb} timed batches")
-    mh_roof = minhash_roofline(wl, shingles, [mh_ms_mean] * args.steps,
+    mh_roof = minhash_roofline(wl, args.workload, shingles, [mh_ms_mean] * args.steps,
                                "k_minhash, one launch per length bucket (incl. the signature pre-fill)")
     mh_roof["timing"] = "HIP events on the pipeline's MinHash stream around each batch's MinHash stage"
     dominant, other = (qi_roof, mh_roof) if qi_ms_mean >= mh_ms_mean else (mh_roof, qi_roof)
