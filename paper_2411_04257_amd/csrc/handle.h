@@ -72,7 +72,12 @@ hipError_t finish_qi(lshbloom *h, hipStream_t s);
 // HIP error).
 // With d_keys (band keys [n][bands]) the keys are taken as given and d_sigs
 // is not read.
+// part 0 enqueues the whole query-insert; when qi_splits(h, n), part 1
+// enqueues its partition passes and part 2 the rest (1 then 2 on one stream
+// is the whole call); otherwise part 1 enqueues everything and part 2 nothing.
 int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n, uint8_t *d_flags, hipStream_t s,
-               const uint64_t *d_keys = nullptr);
+               const uint64_t *d_keys = nullptr, int part = 0);
+// The query-insert of n documents is one binned chunk (so it splits in two).
+bool qi_splits(const lshbloom *h, int64_t n);
 
 }  // namespace lbh

@@ -219,11 +219,20 @@ lb::BloomLaunch bloom_args(lshbloom *h, const uint32_t *sigs, int64_t n) {
 
 namespace lbh {
 
+bool qi_splits(const lshbloom *h, int64_t n_docs) {
+  const bool binned = h->bin_chunk && (h->qi_mode == 2 || (h->qi_mode == 0 && n_docs >= kBinnedMinDocs));
+  return binned && n_docs > 0 && (uint64_t)n_docs <= h->bin_chunk;
+}
+
 int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_flags, hipStream_t s,
-               const uint64_t *d_keys) {
+               const uint64_t *d_keys, int part) {
   hipError_t e;
   const uint64_t pd = (uint64_t)h->prm.bands * h->k;
   const bool binned = h->bin_chunk && (h->qi_mode == 2 || (h->qi_mode == 0 && n_docs >= kBinnedMinDocs));
+  if (part != 0 && !qi_splits(h, n_docs)) {
+    if (part == 2) return LSHBLOOM_OK;
+    part = 0;
+  }
   if (binned) {
     for (int64_t c0 = 0; c0 < n_docs; c0 += (int64_t)h->bin_chunk) {
       const int64_t cn = std::min<int64_t>((int64_t)h->bin_chunk, n_docs - c0);
@@ -254,6 +263,7 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
       a.res0 = h->d_res0;
       a.flags = d_flags + c0;
       a.status = h->d_status;
+      a.cus = (uint32_t)h->cus;
       if (lb::binned_counts_entries(G, h->prm.bands) > h->bin_counts_cap ||
           lb::binned_bucket_entries(G, h->prm.bands) > h->bin_buckets_cap ||
           lb::binned_bin_entries(G, h->prm.bands) > h->bin_bins_cap) {
@@ -261,7 +271,7 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
         h->poisoned = true;
         return LSHBLOOM_EHIP;
       }
-      e = lb::launch_query_insert_binned(a, s);
+      e = lb::launch_query_insert_binned(a, s, part);
       if (e != hipSuccess) return fail_hip(h, e, "query_insert: binned launch");
     }
     return LSHBLOOM_OK;

@@ -51,7 +51,7 @@ struct Slot {
   int64_t *d_desc = nullptr;
   uint32_t *d_sigs = nullptr;
   uint8_t *d_flags = nullptr;
-  hipGraphExec_t g1 = nullptr, g2 = nullptr;
+  hipGraphExec_t g1 = nullptr, g2 = nullptr, g3 = nullptr;
   int64_t ticket = -1, n_docs = 0;
   uint8_t *user_flags = nullptr;
   bool pending = false;
@@ -78,6 +78,13 @@ struct lshbloom_pipeline {
   hipStream_t qi_stream = nullptr;
   hipStream_t mh_stream = nullptr;
   hipStream_t copy_stream = nullptr;
+  // Recorded on the query-insert stream when the partition passes of the
+  // latest enqueued query-insert are done: the next batch's MinHash waits for
+  // it, so that it runs beside the memory-bound bin kernels rather than the
+  // partition passes (whose one-workgroup-per-compute-unit launches leave no
+  // room for MinHash waves).
+  hipEvent_t qi_mid = nullptr;
+  bool has_mid = false;
   Slot slot[kSlots];
   int64_t next_ticket = 0;
   bool tuned = false;
@@ -271,7 +278,10 @@ int autotune(lshbloom_pipeline *pl, Slot &S, const int64_t *off, int64_t n) {
   std::vector<Buckets> cands;
   const uint64_t edge_sets[][3] = {{0, 0, 0}, {512, 0, 0}, {256, 8192, 0}, {64, 1024, 16384}};
   const uint32_t nbs[] = {1, 2, 3, 4};
-  const uint32_t waves[] = {0, 64, 256};  // per compute unit; 0 = by the bucket's tokens
+  // per compute unit; 0 = by the bucket's tokens.  Grids of at most about a
+  // hundred waves per compute unit leave room for the query-insert's bin
+  // kernel beside which the MinHash of the next batch runs.
+  const uint32_t waves[] = {0, 32, 64};
   for (int es = 0; es < 4; ++es)
     for (uint32_t w : waves) {
       Buckets b;
@@ -320,6 +330,7 @@ void free_pipeline(lshbloom_pipeline *pl) {
   for (Slot &S : pl->slot) {
     if (S.g1) (void)hipGraphExecDestroy(S.g1);
     if (S.g2) (void)hipGraphExecDestroy(S.g2);
+    if (S.g3) (void)hipGraphExecDestroy(S.g3);
     if (S.copied) (void)hipEventDestroy(S.copied);
     if (S.mh_done) (void)hipEventDestroy(S.mh_done);
     if (S.done) (void)hipEventDestroy(S.done);
@@ -342,6 +353,7 @@ void free_pipeline(lshbloom_pipeline *pl) {
     (void)hipStreamDestroy(pl->copy_stream);
   }
   if (pl->mh_stream) (void)hipStreamDestroy(pl->mh_stream);
+  if (pl->qi_mid) (void)hipEventDestroy(pl->qi_mid);
 }
 
 // Copy a finished slot's flags to the caller (after its done event), add its
@@ -399,6 +411,7 @@ lshbloom_pipeline_t *lshbloom_pipeline_create(lshbloom_t *h, const lshbloom_pipe
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->qi_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->mh_stream, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&pl->copy_stream, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&pl->qi_mid, hipEventDisableTiming);
   const uint64_t P = h->prm.num_perm;
   for (int q = 0; q < kSlots && e == hipSuccess; ++q) {
     Slot &S = pl->slot[q];
@@ -494,6 +507,7 @@ int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offse
     e = hipMemcpyAsync(S.d_desc, S.h_desc, desc_words(n_docs) * 8, hipMemcpyHostToDevice, pl->copy_stream);
   if (e == hipSuccess) e = hipEventRecord(S.copied, pl->copy_stream);
   if (e == hipSuccess) e = hipStreamWaitEvent(pl->mh_stream, S.copied, 0);
+  if (e == hipSuccess && pl->has_mid) e = hipStreamWaitEvent(pl->mh_stream, pl->qi_mid, 0);
   if (e == hipSuccess) e = hipEventRecord(S.mh_t0, pl->mh_stream);
   if (e != hipSuccess) return fail_hip(nullptr, e, "pipeline: input copy");
   auto g1_body = [&]() -> hipError_t { return enqueue_minhash(pl, S, views, n_docs, bk); };
@@ -511,13 +525,26 @@ int64_t lshbloom_pipeline_submit(lshbloom_pipeline_t *pl, const int64_t *h_offse
     if (e == hipSuccess) e = hipEventRecord(S.qi_t0, pl->qi_stream);
     if (e != hipSuccess) return fail_hip(h, e, "pipeline: ordering");
     int qrc = LSHBLOOM_OK;
+    // partition passes (G2), the event the next MinHash waits for, then the
+    // bins and resolve (G3); a query-insert that does not split runs whole in G2
+    const bool split = lbh::qi_splits(h, n_docs);
     auto g2_body = [&]() -> hipError_t {
-      qrc = lbh::qi_enqueue(h, S.d_sigs, n_docs, S.d_flags, pl->qi_stream);
+      qrc = lbh::qi_enqueue(h, S.d_sigs, n_docs, S.d_flags, pl->qi_stream, nullptr, 1);
+      return qrc ? hipErrorUnknown : hipSuccess;
+    };
+    auto g3_body = [&]() -> hipError_t {
+      qrc = lbh::qi_enqueue(h, S.d_sigs, n_docs, S.d_flags, pl->qi_stream, nullptr, 2);
       return qrc ? hipErrorUnknown : hipSuccess;
     };
     e = pl->prm.use_graph ? run_graph(pl, pl->qi_stream, S.g2, g2_body) : g2_body();
+    if (e == hipSuccess && !qrc && split) e = hipEventRecord(pl->qi_mid, pl->qi_stream);
+    if (e == hipSuccess && !qrc && split)
+      e = pl->prm.use_graph ? run_graph(pl, pl->qi_stream, S.g3, g3_body) : g3_body();
     if (qrc) return qrc;
     if (e != hipSuccess) return fail_hip(h, e, "pipeline: query-insert stage");
+    // a query-insert that did not split has no partition boundary to wait
+    // for: the next MinHash then overlaps it whole
+    pl->has_mid = split;
     e = hipEventRecord(S.qi_t1, pl->qi_stream);
     if (e == hipSuccess) e = lbh::finish_qi(h, pl->qi_stream);
     if (e == hipSuccess)

@@ -53,6 +53,7 @@ struct BinnedLaunch {
   uint8_t *res0;       // [bands][n] probe 0 of (document, band) was set before the document
   uint8_t *flags;      // [n]
   uint32_t *status;
+  uint32_t cus;        // compute units of the device (sizes persistent grids)
 };
 
 // Records per bin aimed at (a bin's wave holds up to 320 in LDS).
@@ -70,6 +71,9 @@ inline uint64_t binned_bucket_entries(const BinnedGeometry &G, uint32_t bands) {
 inline uint64_t binned_bin_entries(const BinnedGeometry &G, uint32_t bands) {
   return (uint64_t)bands * G.bins_per_band + 1;
 }
-hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s);
+// part 0: the whole chunk; part 1: up to and including the partition passes
+// (keys, pass 1, pass 2); part 2: the rest (bins, resolve).  Parts 1 then 2
+// on one stream are the whole chunk.
+hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s, int part = 0);
 
 }  // namespace lb

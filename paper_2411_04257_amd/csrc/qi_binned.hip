@@ -415,6 +415,7 @@ constexpr uint32_t kWPer = kWCap / 64;        // records per lane
 #define LB_BIN_TAB (2 * kWCap)
 #endif
 constexpr uint32_t kWTab = LB_BIN_TAB;        // bit / word table slots (at most 2 per record)
+static_assert(kWTab >= kWCap && kWTab % 64 == 0, "a table slot for every record of a wave-path bin");
 constexpr uint32_t kWRegion = 512;            // direct mode: the bin's words (bin_bits <= 15)
 constexpr uint32_t kMulti = 0x80000000u;
 
@@ -500,17 +501,22 @@ __device__ void bin_global(const BinnedLaunch &A, uint32_t j, uint64_t bin, uint
   wave_sync();
 }
 
-template <bool DIRECT>
-#ifndef LB_BIN_WAVES
-#define LB_BIN_WAVES 1
-#endif
-__global__ __launch_bounds__(64, LB_BIN_WAVES) void k_bq_bin(BinnedLaunch A) {
+// Sparse bins (bin_bits > 15: the bin's words do not fit in LDS): one wave
+// per bin (64-thread workgroups), so that a bin's steps need no workgroup
+// barrier and several bins per SIMD overlap their memory latency.  LDS holds,
+// per wave, the bin's distinct bits (key = local bit + 1, bit 31 marking
+// "probed by two documents or more") with 0 for a bit set before the chunk or
+// 1 + the least document probing it, and a table of the words the records
+// touch with their OR masks; that space then holds the published table, whose
+// entries carry kInit or the least document.  Each record reads its own word
+// from HBM (the state before the chunk).
+__global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
   // tmin[slot]: 0 if the bit was set before the chunk, else 1 + the least
   // document probing it (so one atomicMin serves both), kNoFs before any.
   __shared__ __align__(16) uint32_t tkey[kWTab];
   __shared__ __align__(16) uint32_t tmin[kWTab];
-  __shared__ __align__(16) unsigned long long wv[DIRECT ? kWRegion : kWTab];
-  __shared__ uint32_t wk[DIRECT ? kWRegion / 32 : kWTab];  // direct: changed-word bits; else word keys
+  __shared__ __align__(16) unsigned long long wv[kWTab];
+  __shared__ uint32_t wk[kWTab];  // word keys
 
   const uint32_t lane = threadIdx.x;
   const BinnedGeometry &G = A.G;
@@ -562,62 +568,20 @@ __global__ __launch_bounds__(64, LB_BIN_WAVES) void k_bq_bin(BinnedLaunch A) {
     const uint64_t b0 = lbin << G.bin_bits;  // first bit of the bin (a multiple of 64)
     uint64_t *F = A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6);
     const uint32_t cap = min(2 * nr, kWTab);
-    const uint32_t W = (uint32_t)min((uint64_t)1 << (G.bin_bits - 6), A.words_per_band - (b0 >> 6));
-    // a full bin (every bin but the last of a band) is written back whole
-    const bool full = W == (1u << (G.bin_bits - 6));
-    // this bin's loads first: its words (direct) or each record's word; then
-    // the next bin's records
-    if (DIRECT) {
-      // both tables whole, 16 bytes per store
-      static_assert(kWTab % 4 == 0 && kWTab / 4 <= 192 && kWTab >= kWCap, "three stores per lane");
-      uint4 *k4 = reinterpret_cast<uint4 *>(tkey), *m4 = reinterpret_cast<uint4 *>(tmin);
-      const uint4 z = make_uint4(0u, 0u, 0u, 0u), nf = make_uint4(kNoFs, kNoFs, kNoFs, kNoFs);
 #pragma unroll
-      for (uint32_t t = 0; t < 3; ++t) {
-        const uint32_t q = t * 64 + lane;
-        if ((t + 1) * 64 <= kWTab / 4 || q < kWTab / 4) {
-          k4[q] = z;
-          m4[q] = nf;
-        }
-      }
-    } else {
-#pragma unroll
-      for (uint32_t t = 0; t < kWTab / 64; ++t) {
-        const uint32_t q = t * 64 + lane;
-        if (q < cap) {
-          tkey[q] = 0;
-          tmin[q] = kNoFs;
-          wk[q] = 0;
-          wv[q] = 0;
-        }
+    for (uint32_t t = 0; t < kWTab / 64; ++t) {
+      const uint32_t q = t * 64 + lane;
+      if (q < cap) {
+        tkey[q] = 0;
+        tmin[q] = kNoFs;
+        wk[q] = 0;
+        wv[q] = 0;
       }
     }
-    if (DIRECT && W == kWRegion) {
-      uint64_t reg[kWRegion / 64];
+    // this bin's loads first (each record's word), then the next bin's records
+    uint64_t pre[kWPer];
 #pragma unroll
-      for (uint32_t u = 0; u < kWRegion / 64; ++u) reg[u] = F[u * 64 + lane];
-#pragma unroll
-      for (uint32_t u = 0; u < kWRegion / 64; ++u) wv[u * 64 + lane] = reg[u];
-    } else if (DIRECT) {
-      uint64_t reg[kWRegion / 64];
-#pragma unroll
-      for (uint32_t u = 0; u < kWRegion / 64; ++u) {
-        const uint32_t w = u * 64 + lane;
-        reg[u] = w < W ? F[w] : 0ull;
-      }
-#pragma unroll
-      for (uint32_t u = 0; u < kWRegion / 64; ++u) {
-        const uint32_t w = u * 64 + lane;
-        if (w < W) wv[w] = reg[u];
-      }
-      if (!full && lane < kWRegion / 32) wk[lane] = 0;
-    }
-    uint64_t pre[DIRECT ? 1 : kWPer];
-    if (!DIRECT) {
-#pragma unroll
-      for (uint32_t u = 0; u < kWPer; ++u)
-        pre[u] = u < nu ? F[(uint32_t)((rec[u] & kMask40) - b0) >> 6] : 0ull;
-    }
+    for (uint32_t u = 0; u < kWPer; ++u) pre[u] = u < nu ? F[(uint32_t)((rec[u] & kMask40) - b0) >> 6] : 0ull;
     load_recs(nbin, q0, q1, nrec);
     wave_sync();
     // phase A: insert every record's bit into the bit table.  A lane's
@@ -632,12 +596,9 @@ __global__ __launch_bounds__(64, LB_BIN_WAVES) void k_bq_bin(BinnedLaunch A) {
       key1[u] = 0;
       if (u < nu) {
         const uint32_t lb = (uint32_t)((rec[u] & kMask40) - b0);
-        const uint64_t word = DIRECT ? wv[lb >> 6] : pre[u];
-        init |= (uint32_t)(word >> (lb & 63) & 1ull) << u;
+        init |= (uint32_t)(pre[u] >> (lb & 63) & 1ull) << u;
         key1[u] = lb + 1;
-        // direct bins: the bit itself is uniform over the bin, so it scales
-        // to a slot directly
-        slot[u] = DIRECT ? (uint32_t)(((uint64_t)lb * cap) >> G.bin_bits) : slot_of(lb, cap);
+        slot[u] = slot_of(lb, cap);
       }
     }
     uint32_t pend = 0;
@@ -683,7 +644,7 @@ __global__ __launch_bounds__(64, LB_BIN_WAVES) void k_bq_bin(BinnedLaunch A) {
     // was set before document i iff tmin <= i); a clear bit whose least
     // document is not the reader's was probed by two documents or more; the
     // newly set bits are ORed into the words
-    uint32_t owner = 0, wslot[DIRECT ? 1 : kWPer], wpend = 0;
+    uint32_t owner = 0, wslot[kWPer], wpend = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kWPer; ++u) {
       if (u >= nu) continue;
@@ -693,62 +654,38 @@ __global__ __launch_bounds__(64, LB_BIN_WAVES) void k_bq_bin(BinnedLaunch A) {
       if ((rec[u] & kProbe0) && v <= i) A.res0[(int64_t)j * A.n + i] = 1;
       const bool clr = !(init >> u & 1u);
       if (clr && v != i + 1) atomicOr(&tkey[slot[u]], kMulti);  // rare: skipped by most rows
-      const uint32_t lb = key1[u] - 1, lw = lb >> 6;
-      if (DIRECT) {
-        atomicOr(&wv[lw], clr ? 1ull << (lb & 63) : 0ull);
-        if (!full) atomicOr(&wk[lw >> 5], clr ? 1u << (lw & 31) : 0u);
-      } else if (clr) {
-        wslot[u] = slot_of(lw, cap);
+      if (clr) {
+        wslot[u] = slot_of((key1[u] - 1) >> 6, cap);
         wpend |= 1u << u;
       }
     }
-    if (!DIRECT) {
-      // the word table, in rounds like the bit table; the record that claims
-      // a word's slot writes the word back
-      for (uint32_t round = 0; wpend && round < cap; ++round) {
-        uint32_t old[kWPer];
-#pragma unroll
-        for (uint32_t u = 0; u < kWPer; ++u)
-          if (wpend >> u & 1u) old[u] = atomicCAS(&wk[wslot[u]], 0u, ((key1[u] - 1) >> 6) + 1);
-#pragma unroll
-        for (uint32_t u = 0; u < kWPer; ++u) {
-          if (!(wpend >> u & 1u)) continue;
-          const uint32_t want = ((key1[u] - 1) >> 6) + 1;
-          if (old[u] == 0u) owner |= 1u << u;
-          if (old[u] == 0u || old[u] == want)
-            wpend &= ~(1u << u);
-          else
-            wslot[u] = (wslot[u] + 1 == cap) ? 0 : wslot[u] + 1;
-        }
-      }
-      if (wpend) atomicOr(A.status, 4u);
+    // the word table, in rounds like the bit table; the record that claims a
+    // word's slot writes the word back
+    for (uint32_t round = 0; wpend && round < cap; ++round) {
+      uint32_t old[kWPer];
 #pragma unroll
       for (uint32_t u = 0; u < kWPer; ++u)
-        if (u < nu && !(init >> u & 1u)) atomicOr(&wv[wslot[u]], 1ull << ((key1[u] - 1) & 63));
+        if (wpend >> u & 1u) old[u] = atomicCAS(&wk[wslot[u]], 0u, ((key1[u] - 1) >> 6) + 1);
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u) {
+        if (!(wpend >> u & 1u)) continue;
+        const uint32_t want = ((key1[u] - 1) >> 6) + 1;
+        if (old[u] == 0u) owner |= 1u << u;
+        if (old[u] == 0u || old[u] == want)
+          wpend &= ~(1u << u);
+        else
+          wslot[u] = (wslot[u] + 1 == cap) ? 0 : wslot[u] + 1;
+      }
     }
+    if (wpend) atomicOr(A.status, 4u);
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u)
+      if (u < nu && !(init >> u & 1u)) atomicOr(&wv[wslot[u]], 1ull << ((key1[u] - 1) & 63));
     wave_sync();
     // changed words (this wave is their only writer in the chunk)
-    if (DIRECT && W == kWRegion) {
-      // all of them: nearly every 64-byte sector holds a changed word
 #pragma unroll
-      for (uint32_t t = 0; t < kWRegion / 64; ++t) F[t * 64 + lane] = wv[t * 64 + lane];
-    } else if (DIRECT && full) {
-#pragma unroll
-      for (uint32_t t = 0; t < kWRegion / 64; ++t) {
-        const uint32_t w = t * 64 + lane;
-        if (w < W) F[w] = wv[w];
-      }
-    } else if (DIRECT) {
-#pragma unroll
-      for (uint32_t t = 0; t < kWRegion / 64; ++t) {
-        const uint32_t w = t * 64 + lane;
-        if (w < W && (wk[w >> 5] >> (w & 31) & 1u)) F[w] = wv[w];
-      }
-    } else {
-#pragma unroll
-      for (uint32_t u = 0; u < kWPer; ++u)
-        if (owner >> u & 1u) F[(key1[u] - 1) >> 6] = pre[u] | wv[wslot[u]];
-    }
+    for (uint32_t u = 0; u < kWPer; ++u)
+      if (owner >> u & 1u) F[(key1[u] - 1) >> 6] = pre[u] | wv[wslot[u]];
     // publish the bits a lookup can need (set before the chunk, or probed by
     // two documents or more), each by the record owning its slot, as
     // (local bit + 1) << 32 | (kInit, or the least document)
@@ -770,26 +707,218 @@ __global__ __launch_bounds__(64, LB_BIN_WAVES) void k_bq_bin(BinnedLaunch A) {
     uint32_t mine = 0;
 #pragma unroll
     for (uint32_t u = 0; u < kWPer; ++u) mine += (uint32_t)__popcll(__ballot((ib >> u) & 1u));
-    const uint32_t room = DIRECT ? kWRegion : kWTab;
-    const uint32_t pcap = min(2 * mine, room);
+    const uint32_t pcap = min(2 * mine, kWTab);
     wave_sync();
-    if (DIRECT) {
-      // the table's first pcap entries, two per 16-byte store
-      uint4 *w4 = reinterpret_cast<uint4 *>(wv);
-      const uint4 z = make_uint4(0u, 0u, 0u, 0u);
-      for (uint32_t q = lane; 2 * q < pcap; q += 64) w4[q] = z;
-    } else {
 #pragma unroll
-      for (uint32_t t = 0; t < kWTab / 64; ++t) {
-        const uint32_t q = t * 64 + lane;
-        if (q < pcap) wv[q] = 0;
-      }
+    for (uint32_t t = 0; t < kWTab / 64; ++t) {
+      const uint32_t q = t * 64 + lane;
+      if (q < pcap) wv[q] = 0;
     }
     wave_sync();
 #pragma unroll
     for (uint32_t u = 0; u < kWPer; ++u) {
       if (!(ib >> u & 1u)) continue;
       uint32_t h = slot_of((uint32_t)(ent[u] >> 32) - 1, pcap);
+      for (uint32_t tries = 0; tries < pcap; ++tries) {
+        if (atomicCAS(&wv[h], 0ull, ent[u]) == 0ull) break;
+        h = (h + 1 == pcap) ? 0 : h + 1;
+      }
+    }
+    wave_sync();
+    uint64_t *T = A.rec1 + 2ull * r0;
+    for (uint32_t q = lane; q < pcap; q += 64) T[q] = wv[q];
+    if (lane == 0) A.dir[bin] = ((uint64_t)r0 << 32) | pcap;
+    wave_sync();
+    r0 = q0;
+    r1 = q1;
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
+  }
+}
+
+// Dense bins (bin_bits <= 15: the bin's 512 words fit in LDS): one wave per
+// bin, without a per-record hash table.  Every record sets its bit in an LDS
+// claim bitmap with one atomicOr; the one that finds the bit clear is the
+// bit's first claimer, and every later claimer appends the bit to a short
+// list of shared bits (about one per bin: 231 records over 32,768 bits).
+// Only the records of listed bits then take the least and greatest document
+// probing the bit.  A bit was set before document i iff it was set before
+// the chunk or its least document is below i; it is published for the
+// resolve step (by its first claimer) iff it was set before the chunk or two
+// different documents probe it.  The new words are the old words ORed with
+// the claim bitmap.  A list longer than kListCap sends the bin to bin_global
+// (nothing of it has been written yet).
+constexpr uint32_t kListCap = 64;
+// Persistent grid of the dense bin kernel, waves per compute unit.
+constexpr uint32_t kDenseWavesPerCu = 12;
+
+__global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
+  __shared__ __align__(16) unsigned long long wv[kWRegion];  // the bin's words; then its published table
+  __shared__ __align__(16) unsigned long long cb[kWRegion];  // claim bitmap (the chunk's bits)
+  __shared__ uint32_t lk[kListCap], lmin[kListCap], lmax[kListCap];
+  __shared__ uint32_t ln;
+
+  const uint32_t lane = threadIdx.x;
+  const BinnedGeometry &G = A.G;
+  const uint64_t n_bins = (uint64_t)A.bands * G.bins_per_band;
+  // The records of the wave's next bin are loaded while it works on the
+  // current one; lanes past the bin's end hold ~0 (not a record: document
+  // indices stay below 2^23 - 1).
+  auto load_recs = [&](uint64_t b, uint32_t &q0, uint32_t &q1, uint64_t *out) {
+    q0 = q1 = 0;
+    if (b < n_bins) {
+      q0 = A.off2[b];
+      q1 = A.off2[b + 1];
+    }
+    const bool small = q1 - q0 <= kWCap;
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      const uint32_t r = q0 + u * 64 + lane;
+      out[u] = (small && r < q1) ? A.rec2[r] : ~0ull;
+    }
+  };
+  uint32_t r0, r1;
+  uint64_t rec[kWPer];
+  load_recs(blockIdx.x, r0, r1, rec);
+  for (uint64_t bin = blockIdx.x; bin < n_bins; bin += gridDim.x) {
+    const uint64_t nbin = bin + gridDim.x;
+    uint32_t q0, q1;
+    uint64_t nrec[kWPer];
+    const uint32_t nr = r1 - r0;
+    const uint32_t j = (uint32_t)(bin / G.bins_per_band);
+    const uint64_t b0 = (bin - (uint64_t)j * G.bins_per_band) << G.bin_bits;  // a multiple of 64
+    uint64_t *F = A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6);
+    if (nr == 0 || nr > kWCap) {
+      if (nr > kWCap) bin_global(A, j, bin, r0, r1, b0, F);
+      load_recs(nbin, q0, q1, nrec);
+      r0 = q0;
+      r1 = q1;
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
+      continue;
+    }
+    // the bin's words: 2^(bin_bits - 6) <= kWRegion, fewer in a band's last bin
+    const uint32_t W = (uint32_t)min((uint64_t)1 << (G.bin_bits - 6), A.words_per_band - (b0 >> 6));
+    const bool full = W == kWRegion;
+    // clear the claim bitmap and the list; read the bin's words
+    {
+      uint4 *c4 = reinterpret_cast<uint4 *>(cb);
+      const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+#pragma unroll
+      for (uint32_t t = 0; t < kWRegion / 128; ++t) c4[t * 64 + lane] = z;
+      if (lane == 0) ln = 0;
+      uint64_t reg[kWRegion / 64];
+#pragma unroll
+      for (uint32_t u = 0; u < kWRegion / 64; ++u) {
+        const uint32_t w = u * 64 + lane;
+        reg[u] = (full || w < W) ? F[w] : 0ull;
+      }
+      load_recs(nbin, q0, q1, nrec);
+#pragma unroll
+      for (uint32_t u = 0; u < kWRegion / 64; ++u) wv[u * 64 + lane] = reg[u];
+    }
+    wave_sync();
+    // claims: one atomicOr per record; later claimers list their bit
+    uint32_t lbv[kWPer];
+    uint32_t initm = 0, dupm = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      lbv[u] = ~0u;
+      if (rec[u] == ~0ull) continue;
+      const uint32_t lb = (uint32_t)((rec[u] & kMask40) - b0);
+      lbv[u] = lb;
+      initm |= (uint32_t)(wv[lb >> 6] >> (lb & 63) & 1ull) << u;
+      const unsigned long long bit = 1ull << (lb & 63);
+      const unsigned long long old = atomicOr(&cb[lb >> 6], bit);
+      if (old & bit) dupm |= 1u << u;
+    }
+    if (dupm) {
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u) {
+        if (!(dupm >> u & 1u)) continue;
+        const uint32_t k = atomicAdd(&ln, 1u);
+        if (k < kListCap) {
+          lk[k] = lbv[u];
+          lmin[k] = ~0u;
+          lmax[k] = 0u;
+        }
+      }
+    }
+    wave_sync();
+    const uint32_t nl = ln;
+    if (nl > kListCap) {
+      // more shared bits than the list holds: the general path
+      bin_global(A, j, bin, r0, r1, b0, F);
+      r0 = q0;
+      r1 = q1;
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
+      continue;
+    }
+    // records of listed bits: the first list entry of their bit, and the
+    // least and greatest document probing it
+    uint32_t kix[kWPer];
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) kix[u] = ~0u;
+    if (nl) {
+      for (uint32_t k = 0; k < nl; ++k) {
+        const uint32_t key = lk[k];
+#pragma unroll
+        for (uint32_t u = 0; u < kWPer; ++u)
+          if (kix[u] == ~0u && lbv[u] == key) kix[u] = k;
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kWPer; ++u) {
+        if (kix[u] == ~0u) continue;
+        const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
+        atomicMin(&lmin[kix[u]], i);
+        atomicMax(&lmax[kix[u]], i);
+      }
+      wave_sync();
+    }
+    // probe-0 answers and the entries to publish
+    uint32_t pubm = 0;
+    unsigned long long ent[kWPer];
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      ent[u] = 0;
+      if (lbv[u] == ~0u) continue;
+      const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
+      const bool init = initm >> u & 1u;
+      uint32_t mn = i;
+      bool multi = false;
+      if (kix[u] != ~0u) {
+        mn = lmin[kix[u]];
+        multi = mn != lmax[kix[u]];
+      }
+      // res0 starts zeroed: only the set-before answers are written
+      if ((rec[u] & kProbe0) && (init || mn < i)) A.res0[(int64_t)j * A.n + i] = 1;
+      if (!(dupm >> u & 1u) && (init || multi)) {
+        pubm |= 1u << u;
+        ent[u] = ((unsigned long long)(lbv[u] + 1) << 32) | (init ? kInit : mn);
+      }
+    }
+    // the words after the chunk (this wave is their only writer)
+#pragma unroll
+    for (uint32_t u = 0; u < kWRegion / 64; ++u) {
+      const uint32_t w = u * 64 + lane;
+      if (full || w < W) F[w] = wv[w] | cb[w];
+    }
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) mine += (uint32_t)__popcll(__ballot((pubm >> u) & 1u));
+    const uint32_t pcap = min(2 * mine, kWRegion);
+    wave_sync();
+    {
+      uint4 *w4 = reinterpret_cast<uint4 *>(wv);
+      const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+      for (uint32_t q = lane; 2 * q < pcap; q += 64) w4[q] = z;
+    }
+    wave_sync();
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) {
+      if (!(pubm >> u & 1u)) continue;
+      uint32_t h = slot_of(lbv[u], pcap);
       for (uint32_t tries = 0; tries < pcap; ++tries) {
         if (atomicCAS(&wv[h], 0ull, ent[u]) == 0ull) break;
         h = (h + 1 == pcap) ? 0 : h + 1;
@@ -931,10 +1060,11 @@ BinnedGeometry binned_geometry(uint64_t n_docs, uint32_t bands, uint32_t k, uint
   return G;
 }
 
-hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s) {
-  if (a.n == 0) return hipSuccess;
+namespace {
+
+// Keys, pass 1 and pass 2 of a chunk.
+hipError_t launch_partition(const BinnedLaunch &a, hipStream_t s) {
   const BinnedGeometry &G = a.G;
-  if (G.buckets_per_band > kMaxF1 || G.bins_per_bucket > kMaxF2) return hipErrorInvalidValue;
   hipError_t e;
   const uint32_t td = keys_tile_docs(a.bands * a.rows);
   const size_t ldsk = (size_t)td * (a.bands * a.rows + 1) * 4;
@@ -960,13 +1090,24 @@ hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const size_t lds2 = kSub2 * 8 + 3 * (size_t)G.bins_per_bucket * 4 + 16 * 4;
   hipLaunchKernelGGL(k_bq_part2, dim3(nb), dim3(kT2), lds2, s, a);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// Bins and resolve of a chunk (after its partition).
+hipError_t launch_bins(const BinnedLaunch &a, hipStream_t s) {
+  const BinnedGeometry &G = a.G;
+  hipError_t e;
   const uint64_t n_bins = (uint64_t)a.bands * G.bins_per_band;
-  const unsigned gb = (unsigned)(n_bins < 262144 ? n_bins : 262144);
+  // dense bins: a persistent grid of kDenseWavesPerCu waves per compute unit,
+  // which leaves room on every compute unit for the waves of a MinHash launch
+  // running beside it; sparse bins: one workgroup per bin (at most 262,144),
+  // as many waves as fit, to cover the random reads' latency
+  const uint64_t cap = G.direct_words ? (uint64_t)kDenseWavesPerCu * (a.cus ? a.cus : 256) : 262144;
+  const unsigned gb = (unsigned)(n_bins < cap ? n_bins : cap);
   if (G.direct_words)
-    hipLaunchKernelGGL(k_bq_bin<true>, dim3(gb), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_bq_bin_dense, dim3(gb), dim3(64), 0, s, a);
   else
-    hipLaunchKernelGGL(k_bq_bin<false>, dim3(gb), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(k_bq_bin_sparse, dim3(gb), dim3(64), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // slices of bands per document: enough threads for about 2^18 (document,
   // slice) pairs, at most one band per slice and 256 slices
@@ -974,6 +1115,19 @@ hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s) {
   while (slice_log < 8 && ((uint64_t)a.n << slice_log) < (1ull << 18) && (1u << (slice_log + 1)) <= a.bands) ++slice_log;
   hipLaunchKernelGGL(k_bq_resolve, dim3(grid1((uint64_t)a.n, kThreads >> slice_log)), dim3(kThreads), 0, s, a, slice_log);
   return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s, int part) {
+  if (a.n == 0) return hipSuccess;
+  const BinnedGeometry &G = a.G;
+  if (G.buckets_per_band > kMaxF1 || G.bins_per_bucket > kMaxF2) return hipErrorInvalidValue;
+  if (part != 2) {
+    const hipError_t e = launch_partition(a, s);
+    if (e != hipSuccess || part == 1) return e;
+  }
+  return launch_bins(a, s);
 }
 
 }  // namespace lb
