@@ -806,6 +806,8 @@ def probe_hbm(torch, gb):
     t_copy = timed(lambda: dst.copy_(src))
     t_gather = timed(lambda: torch.index_select(buf, 0, idx, out=vals))
     t_scatter = timed(lambda: buf.index_copy_(0, idx, vals))
+    # random read-modify-writes: accumulate into random words (device atomics)
+    t_atomic = timed(lambda: buf.index_put_((idx,), vals, accumulate=True))
     # The same random accesses into a buffer the size of the 1M-document
     # workload's filters (57.5 MB), which the 256 MB last-level cache holds.
     small_n = 57_510_400 // 8
@@ -820,6 +822,7 @@ def probe_hbm(torch, gb):
         "gather_accesses_per_s": m / (t_gather * 1e-3),
         "gather_GBps_at_64B_sectors": m * 64 / (t_gather * 1e-3) / 1e9,
         "scatter_accesses_per_s": m / (t_scatter * 1e-3),
+        "atomic_add_accesses_per_s": m / (t_atomic * 1e-3),
         "cache_resident_buffer_MB": small_n * 8 / 1e6,
         "cache_resident_gather_accesses_per_s": m / (t_sgather * 1e-3),
         "cache_resident_scatter_accesses_per_s": m / (t_sscatter * 1e-3),
