@@ -5,18 +5,19 @@
 //           that each bucket runs its own persistent MinHash launch with its
 //           own grid), bucket descriptors into pinned memory;
 //   copy stream: H2D tokens + descriptors, one batch after another in
-//           submission order (each copy gets the link to itself; on this
-//           device a host-to-device copy runs as a blit kernel, so copies
-//           of two slots started together would share the link and finish
-//           together, and neither batch's MinHash could start early);
-//   MinHash stream (graph G1 of the batch's slot): after its batch's copy,
+//           submission order (each copy gets the link to itself, so copies of
+//           two batches do not share it and finish together);
+//   MinHash stream (graph G1 of the batch's slot): after its batch's copy and
+//           after the partition passes of the previous batch's query-insert,
 //           signature pre-fill and one MinHash launch per non-empty bucket;
-//   query-insert stream (graph G2): after G1 of this batch and after every
-//           earlier filter call of the handle, the in-order query-insert and
-//           the D2H copy of the flags.
-// Two slots alternate, so the copy of batch t+1 overlaps the MinHash of
-// batch t and the MinHash of batch t+1 its query-insert, while query-inserts
-// stay in submission order.
+//   query-insert stream: after G1 of this batch and after every earlier
+//           filter call of the handle, the partition passes (graph G2), an
+//           event, the bins and resolve (graph G3), then the status word's
+//           and the flags' copies to the host.
+// Two slots of buffers alternate, so the copy of batch t+1 overlaps the
+// query-insert of batch t, and the MinHash of batch t+1 runs beside the bins
+// of batch t (the partition passes fill every compute unit; the bin kernel
+// leaves room), while query-inserts stay in submission order.
 // Per-batch device work is captured into a hipGraph per slot and stage and
 // replayed (the executable graph is updated in place when only launch
 // parameters change).  A small autotuner times candidate bucket edges and
