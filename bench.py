@@ -1,14 +1,14 @@
 #!/usr/bin/env python3
 """End-to-end LSHBloom throughput on one MI355X.
 
-A step is one pass of the whole hot path over one batch of 1M documents:
+A step is one pass of the whole hot path over one batch of documents:
 MinHash signatures of the batch, then the in-order query-insert against the
 per-band Bloom filters (which keep growing across steps, as in a real
 stream).  The default workload is the batched form on the 10M-document
 configuration: synthetic documents (Zipf(1.1) tokens over a 50k vocabulary,
 Pareto(1.5, min 20) lengths capped at 200,000, 25% near-duplicates), 5-token
 shingles, num_perm = 256, 32 bands x 8 rows, filters sized for n = 1e8 at a
-per-band fp rate of 1e-8 (15.3 GB), batches of 1M documents handed over as
+per-band fp rate of 1e-8 (15.3 GB), batches of 2M documents handed over as
 host CSR arrays and flags returned to host memory (the pipeline overlaps the
 copies, length-bucketed MinHash and the query-insert).  Beside it the same
 host batches go through plain per-batch calls, and the same batches through
@@ -833,12 +833,12 @@ def probe_hbm(torch, gb):
 DESCRIPTIONS = {
     "c2": "plain method on GPU: 1M-doc synthetic corpus (Zipf(1.1)/50k-vocab uint32 tokens, lognormal lengths "
           "median 3000 sigma 0.8 cap 50000, 20% near-dups J 0.6-0.95), 5-shingles, num_perm 128, 16 bands x 8 rows, "
-          "filters n=1M fp=1e-6, batches of 65,536",
+          "filters n=1M fp=1e-6, batches of {batch:,}",
     "c3": "batched-form configuration (c3): synthetic corpus with Pareto(1.5, min 20, cap 200k) lengths, "
           "Zipf(1.1)/50k vocab, 25% near-dups; num_perm 256, 32 bands x 8 rows, filters n=100M fp=1e-8 per band "
-          "(15.3 GB), batches of 1M",
+          "(15.3 GB), batches of {batch:,}",
     "c4": "filter-scale query-insert: 1B-signature stream of uniform uint32 (256 wide) with 30% one-band repeats, "
-          "32 bands x 8 rows, filters n=1e9 fp=1e-10 per band (191.7 GB in HBM), batches of 1M",
+          "32 bands x 8 rows, filters n=1e9 fp=1e-10 per band (191.7 GB in HBM), batches of {batch:,}",
     "c5": "serving: Poisson arrivals of 1-4096-document requests (log-uniform), lognormal lengths median 2000 "
           "sigma 0.8, Zipf(1.1)/50k vocab, 15% near-dups of earlier served docs; filters preloaded with 1e8 "
           "documents (num_perm 128, 16 bands x 8 rows, fp 1e-8 per band, 7.7 GB); continuous batching with "
@@ -919,7 +919,7 @@ def main():
         "dtype": "u32",
         "data": "synthetic",
         "config": {
-            "workload": DESCRIPTIONS[args.workload] + stream_note(args, wl),
+            "workload": DESCRIPTIONS[args.workload].format(batch=wl.batch) + stream_note(args, wl),
             "global_batch": wl.batch if args.workload != "c5" else None,
             "docs_timed": res.pop("docs_timed"),
             "parallelism": "single-gpu",

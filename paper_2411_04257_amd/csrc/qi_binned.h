@@ -56,8 +56,13 @@ struct BinnedLaunch {
   uint32_t cus;        // compute units of the device (sizes persistent grids)
 };
 
-// Records per bin aimed at (a bin's wave holds up to 320 in LDS).
+// Records per bin aimed at (a sparse bin's wave holds up to 320).
 constexpr uint32_t kBinTarget = 192;
+// Dense bins (at most 2^15 bits) are widened while they average at most this
+// many records (a dense bin's wave holds up to 576): fewer, fuller bins
+// spread each bin's fixed work (reading, claiming and writing back its
+// words) over more records.
+constexpr uint32_t kDenseFill = 480;
 
 BinnedGeometry binned_geometry(uint64_t n_docs, uint32_t bands, uint32_t k, uint64_t m_bits,
                                uint32_t target_per_bin = kBinTarget);

@@ -740,7 +740,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
 // bin, without a per-record hash table.  Every record sets its bit in an LDS
 // claim bitmap with one atomicOr; the one that finds the bit clear is the
 // bit's first claimer, and every later claimer appends the bit to a short
-// list of shared bits (about one per bin: 231 records over 32,768 bits).
+// list of shared bits (a few per bin: 231 or 462 records over 32,768 bits).
 // Only the records of listed bits then take the least and greatest document
 // probing the bit.  A bit was set before document i iff it was set before
 // the chunk or its least document is below i; it is published for the
@@ -748,9 +748,20 @@ __global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
 // different documents probe it.  The new words are the old words ORed with
 // the claim bitmap.  A list longer than kListCap sends the bin to bin_global
 // (nothing of it has been written yet).
-constexpr uint32_t kListCap = 64;
+#ifndef LB_LIST_CAP
+#define LB_LIST_CAP 64
+#endif
+constexpr uint32_t kListCap = LB_LIST_CAP;
+// Records per bin on the dense path (kDPer per lane): binned_geometry widens
+// dense bins while they average at most kDenseFill records.
+constexpr uint32_t kDPer = 9;
+constexpr uint32_t kDCap = kDPer * 64;
+static_assert(kDPer <= 32, "per-lane record masks are 32-bit");
 // Persistent grid of the dense bin kernel, waves per compute unit.
-constexpr uint32_t kDenseWavesPerCu = 12;
+#ifndef LB_DENSE_WPC
+#define LB_DENSE_WPC 12
+#endif
+constexpr uint32_t kDenseWavesPerCu = LB_DENSE_WPC;
 
 __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
   __shared__ __align__(16) unsigned long long wv[kWRegion];  // the bin's words; then its published table
@@ -770,31 +781,31 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
       q0 = A.off2[b];
       q1 = A.off2[b + 1];
     }
-    const bool small = q1 - q0 <= kWCap;
+    const bool small = q1 - q0 <= kDCap;
 #pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) {
+    for (uint32_t u = 0; u < kDPer; ++u) {
       const uint32_t r = q0 + u * 64 + lane;
       out[u] = (small && r < q1) ? A.rec2[r] : ~0ull;
     }
   };
   uint32_t r0, r1;
-  uint64_t rec[kWPer];
+  uint64_t rec[kDPer];
   load_recs(blockIdx.x, r0, r1, rec);
   for (uint64_t bin = blockIdx.x; bin < n_bins; bin += gridDim.x) {
     const uint64_t nbin = bin + gridDim.x;
     uint32_t q0, q1;
-    uint64_t nrec[kWPer];
+    uint64_t nrec[kDPer];
     const uint32_t nr = r1 - r0;
     const uint32_t j = (uint32_t)(bin / G.bins_per_band);
     const uint64_t b0 = (bin - (uint64_t)j * G.bins_per_band) << G.bin_bits;  // a multiple of 64
     uint64_t *F = A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6);
-    if (nr == 0 || nr > kWCap) {
-      if (nr > kWCap) bin_global(A, j, bin, r0, r1, b0, F);
+    if (nr == 0 || nr > kDCap) {
+      if (nr > kDCap) bin_global(A, j, bin, r0, r1, b0, F);
       load_recs(nbin, q0, q1, nrec);
       r0 = q0;
       r1 = q1;
 #pragma unroll
-      for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
+      for (uint32_t u = 0; u < kDPer; ++u) rec[u] = nrec[u];
       continue;
     }
     // the bin's words: 2^(bin_bits - 6) <= kWRegion, fewer in a band's last bin
@@ -819,10 +830,10 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
     }
     wave_sync();
     // claims: one atomicOr per record; later claimers list their bit
-    uint32_t lbv[kWPer];
+    uint32_t lbv[kDPer];
     uint32_t initm = 0, dupm = 0;
 #pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) {
+    for (uint32_t u = 0; u < kDPer; ++u) {
       lbv[u] = ~0u;
       if (rec[u] == ~0ull) continue;
       const uint32_t lb = (uint32_t)((rec[u] & kMask40) - b0);
@@ -834,7 +845,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
     }
     if (dupm) {
 #pragma unroll
-      for (uint32_t u = 0; u < kWPer; ++u) {
+      for (uint32_t u = 0; u < kDPer; ++u) {
         if (!(dupm >> u & 1u)) continue;
         const uint32_t k = atomicAdd(&ln, 1u);
         if (k < kListCap) {
@@ -852,23 +863,23 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
       r0 = q0;
       r1 = q1;
 #pragma unroll
-      for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
+      for (uint32_t u = 0; u < kDPer; ++u) rec[u] = nrec[u];
       continue;
     }
     // records of listed bits: the first list entry of their bit, and the
     // least and greatest document probing it
-    uint32_t kix[kWPer];
+    uint32_t kix[kDPer];
 #pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) kix[u] = ~0u;
+    for (uint32_t u = 0; u < kDPer; ++u) kix[u] = ~0u;
     if (nl) {
       for (uint32_t k = 0; k < nl; ++k) {
         const uint32_t key = lk[k];
 #pragma unroll
-        for (uint32_t u = 0; u < kWPer; ++u)
+        for (uint32_t u = 0; u < kDPer; ++u)
           if (kix[u] == ~0u && lbv[u] == key) kix[u] = k;
       }
 #pragma unroll
-      for (uint32_t u = 0; u < kWPer; ++u) {
+      for (uint32_t u = 0; u < kDPer; ++u) {
         if (kix[u] == ~0u) continue;
         const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
         atomicMin(&lmin[kix[u]], i);
@@ -878,9 +889,9 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
     }
     // probe-0 answers and the entries to publish
     uint32_t pubm = 0;
-    unsigned long long ent[kWPer];
+    unsigned long long ent[kDPer];
 #pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) {
+    for (uint32_t u = 0; u < kDPer; ++u) {
       ent[u] = 0;
       if (lbv[u] == ~0u) continue;
       const uint32_t i = (uint32_t)(rec[u] >> 40) & kDocMask;
@@ -898,16 +909,27 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
         ent[u] = ((unsigned long long)(lbv[u] + 1) << 32) | (init ? kInit : mn);
       }
     }
+    uint32_t mine = 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kDPer; ++u) mine += (uint32_t)__popcll(__ballot((pubm >> u) & 1u));
+    if (mine > kWRegion) {
+      // more bits to publish than the LDS table holds (a filter nearly full):
+      // the general path; nothing of the bin but probe-0 answers, which it
+      // gives again, has been written
+      bin_global(A, j, bin, r0, r1, b0, F);
+      r0 = q0;
+      r1 = q1;
+#pragma unroll
+      for (uint32_t u = 0; u < kDPer; ++u) rec[u] = nrec[u];
+      continue;
+    }
+    const uint32_t pcap = min(2 * mine, kWRegion);
     // the words after the chunk (this wave is their only writer)
 #pragma unroll
     for (uint32_t u = 0; u < kWRegion / 64; ++u) {
       const uint32_t w = u * 64 + lane;
       if (full || w < W) F[w] = wv[w] | cb[w];
     }
-    uint32_t mine = 0;
-#pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) mine += (uint32_t)__popcll(__ballot((pubm >> u) & 1u));
-    const uint32_t pcap = min(2 * mine, kWRegion);
     wave_sync();
     {
       uint4 *w4 = reinterpret_cast<uint4 *>(wv);
@@ -916,7 +938,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
     }
     wave_sync();
 #pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) {
+    for (uint32_t u = 0; u < kDPer; ++u) {
       if (!(pubm >> u & 1u)) continue;
       uint32_t h = slot_of(lbv[u], pcap);
       for (uint32_t tries = 0; tries < pcap; ++tries) {
@@ -932,7 +954,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
     r0 = q0;
     r1 = q1;
 #pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
+    for (uint32_t u = 0; u < kDPer; ++u) rec[u] = nrec[u];
   }
 }
 
@@ -1032,6 +1054,7 @@ BinnedGeometry binned_geometry(uint64_t n_docs, uint32_t bands, uint32_t k, uint
   const double want = (double)m_bits * target_per_bin / (probes_per_band > 0 ? probes_per_band : 1.0);
   uint32_t s = 6;  // nearest power of two
   while (s < 24 && (double)(1ull << s) * 1.4142135623730951 <= want) ++s;
+  while (s < 15 && probes_per_band * (double)(1ull << (s + 1)) <= (double)kDenseFill * (double)m_bits) ++s;
   G.bin_bits = s;
   G.bins_per_band = (m_bits + (1ull << s) - 1) >> s;
   // at most 2^20 bins per band (1024 x 1024 over the two passes): wider bins

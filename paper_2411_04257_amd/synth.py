@@ -64,7 +64,7 @@ WORKLOADS = {
     "c2": Workload("c2-plain-1M", 1_000_000, ("lognormal", 3000.0, 0.8, 50_000), 0.20, ("jaccard", 0.6, 0.95),
                    128, 16, 8, 1_000_000, 1e-6, 65_536, corpus_seed=3),
     "c3": Workload("c3-batched-10M", 10_000_000, ("pareto", 1.5, 20, 200_000), 0.25, ("jaccard", 0.6, 0.95),
-                   256, 32, 8, 100_000_000, 1e-8, 1_000_000, corpus_seed=4),
+                   256, 32, 8, 100_000_000, 1e-8, 2_000_000, corpus_seed=4),
     "c4": Workload("c4-filter-1B", 1_000_000_000, ("none",), 0.0, ("none",),
                    256, 32, 8, 1_000_000_000, 1e-10, 1_000_000, corpus_seed=5,
                    extra={"repeat_frac": 0.30, "in_batch_frac": 0.5}),

@@ -1,11 +1,11 @@
 """Element-by-element GPU parity at production geometry.
 
-* The 10M-document batched configuration: two 1M-document batches of its
+* The 10M-document batched configuration: two 2M-document batches of its
   recipe through the launch configuration the benchmark times (the pipeline:
   length buckets, hipGraph replay, autotuner, one binned query-insert chunk
-  per batch, 2^15-bit dense bins, 458 pass-1 buckets per band).  Every
-  signature, every flag and every word of the 15.3 GB of filters is compared
-  with the oracle.
+  per batch, 2^15-bit dense bins of about 462 records, 458 pass-1 buckets per
+  band).  Every signature, every flag and every word of the 15.3 GB of
+  filters is compared with the oracle.
 * The filter-scale stream at its per-band shape: 4 bands of 5.99 GB each
   (n = 1e9 at a per-band rate of 1e-10, the share of one GPU of eight under
   band sharding), three 1M-signature chunks (2^18-bit sparse bins, 715

@@ -1,5 +1,5 @@
 """GPU parity at the full sizes of the 10M-document batched workload (one
-1M-document chunk, 15.3 GB of filters) and of the filter-scale stream (1M
+2M-document chunk, 15.3 GB of filters) and of the filter-scale stream (1M
 signatures per chunk, 191.7 GB of filters), in the launch configuration the
 benchmark times (binned query-insert, one chunk per batch).
 
