@@ -409,7 +409,10 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
 // words (direct mode) or a table of the words it touches with their OR masks;
 // that space then holds the published table, whose entries carry kInit or
 // the least document.
-constexpr uint32_t kWCap = 320;               // records per bin on the wave path
+#ifndef LB_WCAP
+#define LB_WCAP 320
+#endif
+constexpr uint32_t kWCap = LB_WCAP;           // records per bin on the sparse wave path
 constexpr uint32_t kWPer = kWCap / 64;        // records per lane
 #ifndef LB_BIN_TAB
 #define LB_BIN_TAB (2 * kWCap)
