@@ -67,12 +67,14 @@ def profile_rows(name: str, tag: str) -> dict:
     return out
 
 
-def qi_traffic(workload: str):
+def qi_traffic(key: str):
     """HBM bytes per batch of the query-insert kernels from the counter runs
     in profiles/query_insert_counters.md (FETCH_SIZE and WRITE_SIZE, scaled by
-    a plain copy), for the kernel version built here; None otherwise."""
+    a plain copy), for the kernel version built here and the workload and
+    batch size `key` names ("<workload>_b<documents per batch>"); None
+    otherwise."""
     rows = profile_rows("query_insert_counters.md", source_tag("qi_binned.hip", "qi_binned.h", "device_math.h"))
-    r = rows.get(workload)
+    r = rows.get(key)
     return None if r is None else r[0] + r[1]
 
 
@@ -206,7 +208,7 @@ def qi_roofline(wl, args, batch, probes, new_bits, qi_ms, filter_bytes, traffic_
     steps = len(qi_ms)
     per_batch = qi_algorithmic_bytes(steps, batch, probes, new_bits, wl.num_perm) / steps
     ach = per_batch / (float(np.mean(qi_ms)) * 1e-3)
-    traffic = qi_traffic(traffic_key) if traffic_key else None
+    traffic = qi_traffic(f"{traffic_key}_b{batch}") if traffic_key else None
     roof = {
         "bound": "hbm",
         "kernel": "query-insert (all kernels of a batch's in-order test-and-set)",
