@@ -293,6 +293,42 @@ def test_query_insert_identical_documents_sparse_bins(gpu, qi_mode):
     assert want[501:3500].all() and not want[500]
 
 
+def test_query_insert_dense_bins_over_saturated_filters(gpu):
+    """Dense bins whose published bits outgrow the LDS table: one band of
+    4.19M bits (128 bins of 2^15 bits) whose words are 99% set before the
+    call, and 20,400 random signatures with k = 3 (about 478 probes per bin
+    on average, so the geometry keeps 2^15-bit dense bins).  In the fullest
+    bins more than 512 distinct bits were set before the chunk, so more than
+    512 entries would need publishing: those bins must take the global-table
+    path.  Flags (most documents are false positives of the saturated
+    filter, the rest depend on every lookup) and filters equal the oracle's
+    (Section 2.1)."""
+    rng = np.random.default_rng(41)
+    P, n, p = 64, 969_000, 0.125
+    g, o = _pair(gpu, num_perm=P, bands=1, rows=P, n=n, fp=p, chunk_docs=32768, qi_mode=2)
+    assert (o.m_bits, o.k) == (4_193_920, 3)
+    bits = rng.random((o.words_per_band, 64)) < 0.99
+    words = np.packbits(bits, axis=1, bitorder="little").view(np.uint64).reshape(1, -1)
+    o.set_filters(words)
+    g.write_filters(torch.as_tensor(words.view(np.int64)).cuda())
+    sigs = _random_sigs(rng, 20_400, P)
+    # the case is reached: some 2^15-bit region holds more than 512 distinct
+    # probed bits that were set before the call
+    keys = o.band_keys(sigs)
+    _, _, salts = o.coeffs()
+    pos = np.concatenate([oracle.positions(int(kk), salts[1], salts[2], o.m_bits, o.k) for kk in keys[:, 0]])
+    pre = (words[0][(pos >> 6).astype(np.int64)] >> (pos & np.uint64(63))) & np.uint64(1)
+    full = np.unique(pos[pre == 1])
+    assert np.bincount((full >> 15).astype(np.int64)).max() > 512
+    want = o.query_insert(sigs)
+    got = g.query_insert(torch.as_tensor(sigs.view(np.int32)).cuda()).cpu().numpy()
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(g.read_filters().cpu().numpy().view(np.uint64), o.filters())
+    assert g.info()["device_status"] == 0
+    assert 0.9 < want.mean() < 1.0
+    g.close()
+
+
 @QI_MODES
 def test_query_insert_largest_signature_and_band_counts(gpu, qi_mode):
     """The limits of the handle: 512-value signatures, 64 bands of 8 rows,
