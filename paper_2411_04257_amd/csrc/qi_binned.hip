@@ -335,28 +335,34 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
   sync_lds();
   // The first sub-tile's records stay in registers from the counting pass to
   // the splitting pass, so that a bucket of at most kSub2 records is read once.
+  // The counting pass needs only a record's bin within its bucket, bits
+  // [bin_bits, bucket_bits) of its bit, all in the record's low 32 bits
+  // (bucket_bits <= 32 is checked at launch): the later sub-tiles load only
+  // those.
+  const uint32_t *lo1 = reinterpret_cast<const uint32_t *>(A.rec1);
+  const uint32_t bmask = F2 - 1;
   uint64_t rec[kPer2];
   {
-    uint64_t g[kPer2];
+    uint32_t bi[kPer2];
 #pragma unroll
     for (uint32_t u = 0; u < kPer2; ++u) {
       const uint32_t r = s0 + u * kT2 + threadIdx.x;
-      g[u] = r < s1 ? A.rec1[r] : ~0ull;
-      rec[u] = g[u];
+      rec[u] = r < s1 ? A.rec1[r] : ~0ull;
+      bi[u] = r < s1 ? ((uint32_t)rec[u] >> G.bin_bits) & bmask : ~0u;
     }
     for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
-      uint32_t bi[kPer2];
-#pragma unroll
-      for (uint32_t u = 0; u < kPer2; ++u)
-        bi[u] = g[u] != ~0ull ? (uint32_t)(((g[u] & kMask40) >> G.bin_bits) - first_bin) : ~0u;
+      uint32_t g[kPer2];
 #pragma unroll
       for (uint32_t u = 0; u < kPer2; ++u) {
         const uint32_t r = q0 + kSub2 + u * kT2 + threadIdx.x;
-        g[u] = r < s1 ? A.rec1[r] : ~0ull;
+        g[u] = r < s1 ? lo1[2ull * r] : 0u;
       }
 #pragma unroll
       for (uint32_t u = 0; u < kPer2; ++u)
         if (bi[u] != ~0u) atomicAdd(&cur[bi[u]], 1u);
+#pragma unroll
+      for (uint32_t u = 0; u < kPer2; ++u)
+        bi[u] = q0 + kSub2 + u * kT2 + threadIdx.x < s1 ? (g[u] >> G.bin_bits) & bmask : ~0u;
     }
   }
   sync_lds();
@@ -966,6 +972,11 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
 // block, chosen so that a chunk of few documents still fills the device);
 // thread (slice, document) walks its slice's bands in order and stops at the
 // first match, and the slices' answers meet in LDS.
+#ifndef LB_RES_GROUP
+#define LB_RES_GROUP 4
+#endif
+constexpr uint32_t kResGroup = LB_RES_GROUP;  // probes whose lookups are issued together
+
 __global__ __launch_bounds__(256) void k_bq_resolve(BinnedLaunch A, uint32_t slice_log) {
   __shared__ uint32_t fl[kThreads];
   const uint32_t per = kThreads >> slice_log;          // documents per block
@@ -982,18 +993,18 @@ __global__ __launch_bounds__(256) void k_bq_resolve(BinnedLaunch A, uint32_t sli
     const uint64_t key = A.keys[(int64_t)j * A.n + i];
     const uint64_t h1 = fmix64(key ^ A.salt1), h2 = fmix64(key ^ A.salt2) | 1ull;
     bool hit = true;
-    // Probes 1..k-1 in groups of four: the four directory entries and the
-    // four first table slots are loaded before any is examined, so that a
+    // Probes 1..k-1 in groups of kResGroup (four): the group's directory
+    // entries and first table slots are loaded before any is examined, so that a
     // band whose probes all hit waits for k/4 rounds of dependent loads, not
     // k.  The answer is the same conjunction; the extra reads of a group
     // after a miss are reads of valid tables.
-    for (uint32_t l0 = 1; l0 < A.k && hit; l0 += 4) {
-      const uint32_t nl = min(4u, A.k - l0);
-      uint32_t lb[4], pcap[4], h[4];
-      const uint64_t *T[4];
-      uint64_t e[4];
+    for (uint32_t l0 = 1; l0 < A.k && hit; l0 += kResGroup) {
+      const uint32_t nl = min(kResGroup, A.k - l0);
+      uint32_t lb[kResGroup], pcap[kResGroup], h[kResGroup];
+      const uint64_t *T[kResGroup];
+      uint64_t e[kResGroup];
 #pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) {
+      for (uint32_t u = 0; u < kResGroup; ++u) {
         pcap[u] = 0;
         if (u < nl) {
           const uint64_t g = umulhi64(h1 + (uint64_t)(l0 + u) * h2, A.m_bits);
@@ -1005,12 +1016,12 @@ __global__ __launch_bounds__(256) void k_bq_resolve(BinnedLaunch A, uint32_t sli
         }
       }
 #pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) {
+      for (uint32_t u = 0; u < kResGroup; ++u) {
         h[u] = pcap[u] ? slot_of(lb[u], pcap[u]) : 0;
         e[u] = pcap[u] ? T[u][h[u]] : 0;
       }
 #pragma unroll
-      for (uint32_t u = 0; u < 4; ++u) {
+      for (uint32_t u = 0; u < kResGroup; ++u) {
         if (u >= nl || !hit) break;
         bool found = false;
         uint32_t v = 0;
@@ -1148,7 +1159,7 @@ hipError_t launch_bins(const BinnedLaunch &a, hipStream_t s) {
 hipError_t launch_query_insert_binned(const BinnedLaunch &a, hipStream_t s, int part) {
   if (a.n == 0) return hipSuccess;
   const BinnedGeometry &G = a.G;
-  if (G.buckets_per_band > kMaxF1 || G.bins_per_bucket > kMaxF2) return hipErrorInvalidValue;
+  if (G.buckets_per_band > kMaxF1 || G.bins_per_bucket > kMaxF2 || G.bucket_bits > 32) return hipErrorInvalidValue;
   if (part != 2) {
     const hipError_t e = launch_partition(a, s);
     if (e != hipSuccess || part == 1) return e;
