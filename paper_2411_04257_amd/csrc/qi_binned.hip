@@ -758,7 +758,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
 // the claim bitmap.  A list longer than kListCap sends the bin to bin_global
 // (nothing of it has been written yet).
 #ifndef LB_LIST_CAP
-#define LB_LIST_CAP 64
+#define LB_LIST_CAP 96
 #endif
 constexpr uint32_t kListCap = LB_LIST_CAP;
 // Records per bin on the dense path (kDPer per lane): binned_geometry widens
