@@ -35,7 +35,8 @@ struct lshbloom {
   uint64_t bin_counts_cap = 0;  // entries of the pass-1 count/offset array
   uint64_t bin_buckets_cap = 0; // bucket starts
   uint64_t bin_bins_cap = 0;    // bin offsets / directory
-  uint32_t *d_counts1 = nullptr, *d_bstart = nullptr, *d_off2 = nullptr;
+  uint64_t bin_rec2_cap = 0;    // binned-record slots (records plus pass 2's spare slices)
+  uint32_t *d_counts1 = nullptr, *d_bstart = nullptr, *d_off2 = nullptr, *d_end2 = nullptr;
   uint64_t *d_rec1 = nullptr, *d_rec2 = nullptr, *d_bkeys = nullptr, *d_dir = nullptr;
   uint8_t *d_res0 = nullptr;
   int minhash_waves = 0;  // persistent MinHash grid; 0 = sized per call

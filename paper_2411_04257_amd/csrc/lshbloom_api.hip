@@ -126,6 +126,7 @@ void free_all(lshbloom *h) {
   if (h->d_counts1) (void)hipFree(h->d_counts1);
   if (h->d_bstart) (void)hipFree(h->d_bstart);
   if (h->d_off2) (void)hipFree(h->d_off2);
+  if (h->d_end2) (void)hipFree(h->d_end2);
   if (h->d_dir) (void)hipFree(h->d_dir);
   if (h->d_rec1) (void)hipFree(h->d_rec1);
   if (h->d_rec2) (void)hipFree(h->d_rec2);
@@ -259,6 +260,17 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
       a.rec1 = h->d_rec1;
       a.rec2 = h->d_rec2;
       a.off2 = h->d_off2;
+      a.end2 = h->d_end2;
+      {
+        // pass 2 reads each bucket once when buckets are large and the
+        // workspace holds their spare slices; otherwise it counts first (the
+        // same result)
+        const uint64_t slots = lb::binned_slice_slots(G, h->prm.bands, a.n_records);
+        const uint64_t buckets = (uint64_t)h->prm.bands * G.buckets_per_band;
+        a.slice_slack = slots <= h->bin_rec2_cap && slots < (1ull << 32) && a.n_records >= buckets * lb::kSliceMinBucket
+                            ? lb::binned_slice_slack(a.n_records, (uint64_t)h->prm.bands * G.bins_per_band)
+                            : 0u;
+      }
       a.dir = h->d_dir;
       a.res0 = h->d_res0;
       a.flags = d_flags + c0;
@@ -429,10 +441,13 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   h->chunk_docs = chunk;
   h->table_slots_max = slots;
 
-  // Binned query-insert: 24 bytes per probe of a chunk (pass-1 records, 8 B,
-  // whose space then holds the published tables, 2 x 8 B per record, and the
-  // binned records, 8 B) plus 9 bytes per (document, band) (band keys and
-  // probe-0 answers) and the count, bucket and bin arrays.
+  // Binned query-insert: 24 bytes per binned-record slot (pass-1 records,
+  // 8 B per probe, whose space then holds the published tables, 2 x 8 B per
+  // slot, and the binned records, 8 B per slot) plus 9 bytes per (document,
+  // band) (band keys and probe-0 answers) and the count, bucket and bin
+  // arrays.  A slot per probe, plus the spare slices that let pass 2 read
+  // each bucket once (about a quarter more); a chunk sized from the budget
+  // leaves room for them.
   h->qi_mode = prm.qi_mode;
   if (const char *qm = std::getenv("LSHBLOOM_QI_MODE")) {
     if (!std::strcmp(qm, "direct")) h->qi_mode = 1;
@@ -441,7 +456,7 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
   uint64_t bin_chunk = 0, bin_ws = 0;
   if (h->qi_mode != 1) {
     const uint64_t budget = prm.workspace_budget ? prm.workspace_budget : (4ull << 30);
-    const uint64_t per_doc = 24 * probes_per_doc + 9ull * prm.bands;
+    const uint64_t per_doc = 32 * probes_per_doc + 9ull * prm.bands;
     bin_chunk = prm.chunk_docs ? prm.chunk_docs : budget / per_doc;
     if (!prm.chunk_docs) bin_chunk = std::min<uint64_t>(bin_chunk, std::max<uint64_t>(prm.expected_n, 65536));
     bin_chunk = std::min<uint64_t>(bin_chunk, lb::kBinnedMaxDocs);                       // document field
@@ -452,7 +467,12 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
     h->bin_counts_cap = lb::binned_counts_entries(g, prm.bands);
     h->bin_buckets_cap = lb::binned_bucket_entries(g, prm.bands);
     h->bin_bins_cap = lb::binned_bin_entries(g, prm.bands);
-    bin_ws = bin_chunk * per_doc + h->bin_counts_cap * 4 + h->bin_buckets_cap * 4 + h->bin_bins_cap * 12;
+    const uint64_t records = bin_chunk * probes_per_doc;
+    const uint64_t sliced = lb::binned_slice_slots(g, prm.bands, records);
+    const bool room = prm.chunk_docs || (sliced - records) * 24 + bin_chunk * (24 * probes_per_doc + 9ull * prm.bands) <= budget;
+    h->bin_rec2_cap = room && sliced < (1ull << 32) ? sliced : records;
+    bin_ws = h->bin_rec2_cap * 24 + bin_chunk * 9ull * prm.bands + h->bin_counts_cap * 4 + h->bin_buckets_cap * 4 +
+             h->bin_bins_cap * 16;
   }
   h->bin_chunk = bin_chunk;
   const uint64_t hitb_docs = chunk;
@@ -514,9 +534,10 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
     LB_ALLOC(h->d_counts1, h->bin_counts_cap * 4);
     LB_ALLOC(h->d_bstart, h->bin_buckets_cap * 4);
     LB_ALLOC(h->d_off2, h->bin_bins_cap * 4);
+    LB_ALLOC(h->d_end2, h->bin_bins_cap * 4);
     LB_ALLOC(h->d_dir, h->bin_bins_cap * 8);
-    LB_ALLOC(h->d_rec1, bin_chunk * probes_per_doc * 16);
-    LB_ALLOC(h->d_rec2, bin_chunk * probes_per_doc * 8);
+    LB_ALLOC(h->d_rec1, h->bin_rec2_cap * 16);
+    LB_ALLOC(h->d_rec2, h->bin_rec2_cap * 8);
     LB_ALLOC(h->d_bkeys, bin_chunk * prm.bands * 8);
     LB_ALLOC(h->d_res0, (bin_chunk * prm.bands + 15) & ~15ull);  // zeroed as 32-bit words
   }

@@ -299,10 +299,20 @@ __global__ __launch_bounds__(256) void k_bq_scan_buckets(BinnedLaunch A) {
 }
 
 // ---------------------------------------------------------------- pass 2 ----
-// One 1024-thread block per bucket (one block fills a compute unit's LDS):
-// count its bins, publish their record ranges, and split the bucket into
-// bins through LDS-staged sub-tiles of 16,384 records, so that each bin's
-// share of a sub-tile leaves as one contiguous run.
+// One 1024-thread block per bucket (one block fills a compute unit's LDS)
+// splits the bucket into bins through LDS-staged sub-tiles of 16,384
+// records, so that each bin's share of a sub-tile leaves as one contiguous
+// run, and publishes every bin's record range [start, end).
+//
+// Bucket q owns the binned-record region that starts at bstart[q] +
+// q (slack + 1) F2 and holds its T records plus (slack + 1) F2 spare slots.
+// With slack > 0 each bin first gets a slice of ceil(T / bins) + slack slots
+// (slack is about five standard deviations of a bin's record count), so the
+// bucket is read once; a bin that outgrows its slice (a skewed bucket) makes
+// the block lay the bucket out again, compactly, from its exact bin counts.
+// With slack = 0 (smaller buckets, where a second read costs less than the
+// slices' partial-line writes, or no spare slots in the workspace) the block
+// counts first, then splits compactly.
 #ifndef LB_T2
 #define LB_T2 1024
 #endif
@@ -318,31 +328,100 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
   const BinnedGeometry &G = A.G;
   const uint32_t F2 = G.bins_per_bucket;
   uint64_t *stage = (uint64_t *)smem;            // [kSub2]
-  uint32_t *cur = (uint32_t *)(stage + kSub2);   // [F2]
+  uint32_t *cur = (uint32_t *)(stage + kSub2);   // [F2] next write position of each bin
   uint32_t *h = cur + F2;                        // [F2]
   uint32_t *lstart = h + F2;                     // [F2]
   uint32_t *part = lstart + F2;                  // [16]
+  uint32_t *ovf = part + 16;                     // [1] a bin outgrew its slice
 
   const uint32_t q = blockIdx.x;
   const uint32_t j = q / G.buckets_per_band, f = q - j * G.buckets_per_band;
   const uint32_t s0 = A.bstart[q], s1 = A.bstart[q + 1];
   const uint64_t first_bin = (uint64_t)f * F2;  // within the band
-  const uint64_t nbins = min((uint64_t)F2, G.bins_per_band - first_bin);
+  const uint32_t nbins = (uint32_t)min((uint64_t)F2, G.bins_per_band - first_bin);
+  const uint32_t slack = A.slice_slack;
+  const uint32_t base2 = s0 + (slack ? q * (slack + 1) * F2 : 0u);
+  const uint32_t capb = slack ? (s1 - s0 + nbins - 1) / nbins + slack : 0u;  // slice of each bin
+  const uint32_t bmask = F2 - 1;
+  uint32_t *start = A.off2 + (uint64_t)j * G.bins_per_band + first_bin;
+  uint32_t *end = A.end2 + (uint64_t)j * G.bins_per_band + first_bin;
+
+  // Split the bucket: every record goes to cur[bin] + its rank among the
+  // bin's records so far; with `limit`, a position at or past the bin's
+  // slice end is not written and raises *ovf.  rec[] holds the first
+  // sub-tile (loaded here unless `loaded`); the next sub-tile's records are
+  // loaded as soon as the current ones sit in LDS, so that their latency
+  // overlaps the write-out and the barriers.
+  uint64_t rec[kPer2];
+  auto split = [&](bool limit, bool loaded) {
+    if (!loaded) {
+#pragma unroll
+      for (uint32_t u = 0; u < kPer2; ++u) {
+        const uint32_t r = s0 + u * kT2 + threadIdx.x;
+        rec[u] = r < s1 ? A.rec1[r] : ~0ull;
+      }
+    }
+    for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
+      uint32_t rk[kPer2];
+#pragma unroll
+      for (uint32_t u = 0; u < kPer2; ++u)
+        if (rec[u] != ~0ull) rk[u] = atomicAdd(&h[((uint32_t)rec[u] >> G.bin_bits) & bmask], 1u);
+      sync_lds();
+      const uint32_t cnt = block_scan<kT2>(h, lstart, F2, part);
+#pragma unroll
+      for (uint32_t u = 0; u < kPer2; ++u)
+        if (rec[u] != ~0ull) stage[lstart[((uint32_t)rec[u] >> G.bin_bits) & bmask] + rk[u]] = rec[u];
+#pragma unroll
+      for (uint32_t u = 0; u < kPer2; ++u) {
+        const uint32_t r = q0 + kSub2 + u * kT2 + threadIdx.x;
+        rec[u] = r < s1 ? A.rec1[r] : ~0ull;
+      }
+      sync_lds();
+      for (uint32_t p = threadIdx.x; p < cnt; p += kT2) {
+        const uint64_t r = stage[p];
+        const uint32_t b = ((uint32_t)r >> G.bin_bits) & bmask;
+        const uint32_t w = cur[b] + (p - lstart[b]);
+        if (!limit || w < base2 + (b + 1) * capb)
+          A.rec2[w] = r;
+        else
+          *ovf = 1u;
+      }
+      sync_lds();
+      for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
+        cur[b] += h[b];
+        h[b] = 0;
+      }
+      sync_lds();
+    }
+  };
+
   for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
-    cur[b] = 0;
+    cur[b] = slack ? base2 + b * capb : 0u;
     h[b] = 0;
   }
+  if (threadIdx.x == 0) *ovf = 0u;
   sync_lds();
-  // The first sub-tile's records stay in registers from the counting pass to
-  // the splitting pass, so that a bucket of at most kSub2 records is read once.
-  // The counting pass needs only a record's bin within its bucket, bits
-  // [bin_bits, bucket_bits) of its bit, all in the record's low 32 bits
-  // (bucket_bits <= 32 is checked at launch): the later sub-tiles load only
-  // those.
-  const uint32_t *lo1 = reinterpret_cast<const uint32_t *>(A.rec1);
-  const uint32_t bmask = F2 - 1;
-  uint64_t rec[kPer2];
-  {
+  bool loaded = false;
+  if (slack) {
+    split(true, false);
+    if (*ovf == 0u) {
+      for (uint32_t b = threadIdx.x; b < nbins; b += kT2) {
+        start[b] = base2 + b * capb;
+        end[b] = cur[b];
+      }
+      return;
+    }
+    // a bin outgrew its slice: its exact count is known; lay the bucket out
+    // compactly in its region instead
+    for (uint32_t b = threadIdx.x; b < F2; b += kT2) cur[b] -= base2 + b * capb;
+  } else {
+    // count the bins first.  The first sub-tile's records stay in registers
+    // for the split, so that a bucket of at most kSub2 records is read once;
+    // the counting pass needs only a record's bin within its bucket, bits
+    // [bin_bits, bucket_bits) of its bit, all in the record's low 32 bits
+    // (bucket_bits <= 32 is checked at launch), so the later sub-tiles load
+    // only those
+    const uint32_t *lo1 = reinterpret_cast<const uint32_t *>(A.rec1);
     uint32_t bi[kPer2];
 #pragma unroll
     for (uint32_t u = 0; u < kPer2; ++u) {
@@ -364,46 +443,17 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
       for (uint32_t u = 0; u < kPer2; ++u)
         bi[u] = q0 + kSub2 + u * kT2 + threadIdx.x < s1 ? (g[u] >> G.bin_bits) & bmask : ~0u;
     }
+    loaded = true;
   }
   sync_lds();
   block_scan<kT2>(cur, cur, F2, part);
   for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
-    cur[b] += s0;
-    if (b < nbins) A.off2[(uint64_t)j * G.bins_per_band + first_bin + b] = cur[b];
+    cur[b] += base2;
+    if (b < nbins) start[b] = cur[b];
   }
-  if (q + 1 == A.bands * G.buckets_per_band && threadIdx.x == 0)
-    A.off2[(uint64_t)A.bands * G.bins_per_band] = A.n_records;
   sync_lds();
-  // The next sub-tile's records are loaded as soon as the current ones sit in
-  // LDS, so that their latency overlaps the write-out and the barriers.
-  for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
-    uint32_t rk[kPer2];
-#pragma unroll
-    for (uint32_t u = 0; u < kPer2; ++u)
-      if (rec[u] != ~0ull) rk[u] = atomicAdd(&h[(uint32_t)(((rec[u] & kMask40) >> G.bin_bits) - first_bin)], 1u);
-    sync_lds();
-    const uint32_t cnt = block_scan<kT2>(h, lstart, F2, part);
-#pragma unroll
-    for (uint32_t u = 0; u < kPer2; ++u)
-      if (rec[u] != ~0ull) stage[lstart[(uint32_t)(((rec[u] & kMask40) >> G.bin_bits) - first_bin)] + rk[u]] = rec[u];
-#pragma unroll
-    for (uint32_t u = 0; u < kPer2; ++u) {
-      const uint32_t r = q0 + kSub2 + u * kT2 + threadIdx.x;
-      rec[u] = r < s1 ? A.rec1[r] : ~0ull;
-    }
-    sync_lds();
-    for (uint32_t p = threadIdx.x; p < cnt; p += kT2) {
-      const uint64_t r = stage[p];
-      const uint32_t b = (uint32_t)(((r & kMask40) >> G.bin_bits) - first_bin);
-      A.rec2[cur[b] + (p - lstart[b])] = r;
-    }
-    sync_lds();
-    for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
-      cur[b] += h[b];
-      h[b] = 0;
-    }
-    sync_lds();
-  }
+  split(false, loaded);
+  for (uint32_t b = threadIdx.x; b < nbins; b += kT2) end[b] = cur[b];
 }
 
 // ------------------------------------------------------------------- bins ----
@@ -540,7 +590,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
     q0 = q1 = 0;
     if (b < n_bins) {
       q0 = A.off2[b];
-      q1 = A.off2[b + 1];
+      q1 = A.end2[b];
     }
     const uint32_t nrr = q1 - q0;
     const bool small = nrr <= kWCap;
@@ -788,7 +838,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
     q0 = q1 = 0;
     if (b < n_bins) {
       q0 = A.off2[b];
-      q1 = A.off2[b + 1];
+      q1 = A.end2[b];
     }
     const bool small = q1 - q0 <= kDCap;
 #pragma unroll
@@ -1125,7 +1175,7 @@ hipError_t launch_partition(const BinnedLaunch &a, hipStream_t s) {
   const size_t lds1 = kSub1 * 8 + 3 * (size_t)((G.buckets_per_band + 3) & ~3u) * 4 + 16 * 4;
   hipLaunchKernelGGL(k_bq_scatter1, dim3(G.n_tiles, a.bands), dim3(kT1), lds1, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds2 = kSub2 * 8 + 3 * (size_t)G.bins_per_bucket * 4 + 16 * 4;
+  const size_t lds2 = kSub2 * 8 + 3 * (size_t)G.bins_per_bucket * 4 + 17 * 4;
   hipLaunchKernelGGL(k_bq_part2, dim3(nb), dim3(kT2), lds2, s, a);
   return hipGetLastError();
 }
