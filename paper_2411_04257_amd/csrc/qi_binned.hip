@@ -12,7 +12,7 @@
 //                 [probe-0 flag : 1][document : 23][bit position : 40]
 //             into buckets of consecutive bins, staging each 16,384-record
 //             sub-tile in LDS so that every bucket's records leave as one
-//             contiguous run;
+//             contiguous run; each XCD takes a contiguous range of tiles;
 //   pass 2    (k_bq_part2): one block per bucket counts its bins, publishes
 //             their record ranges and splits the bucket the same way;
 //   bins      (k_bq_bin): one wave per bin reads the bin's filter words
@@ -189,11 +189,25 @@ constexpr uint32_t kT1 = kTileDocs;
 constexpr uint32_t kPer1 = LB_PER1;
 constexpr uint32_t kSub1 = kT1 * kPer1;
 
+// Pass-1 blocks, renumbered so that each of the 8 XCDs (which take the
+// launch's blocks in turn) works through a contiguous range of (band, tile)
+// pairs: neighbouring tiles' writes to a bucket, whose ends share lines, then
+// meet in one L2.
+__device__ __forceinline__ void pass1_block(uint32_t n_tiles, uint32_t &tile, uint32_t &band) {
+  const uint32_t total = gridDim.x * gridDim.y;
+  const uint32_t L = blockIdx.x + gridDim.x * blockIdx.y;
+  const uint32_t x = L & 7u, i = L >> 3, q = total >> 3, r = total & 7u;
+  const uint32_t P = x * q + min(x, r) + i;
+  tile = P % n_tiles;
+  band = P / n_tiles;
+}
+
 __global__ __launch_bounds__(256) void k_bq_count1(BinnedLaunch A) {
   extern __shared__ uint32_t hist[];  // [F1]
   const BinnedGeometry &G = A.G;
   const uint32_t F1 = G.buckets_per_band;
-  const uint32_t j = blockIdx.y, tile = blockIdx.x;
+  uint32_t tile, j;
+  pass1_block(G.n_tiles, tile, j);
   const int64_t d0 = (int64_t)tile * kTileDocs;
   const uint32_t nd = (uint32_t)min((int64_t)kTileDocs, A.n - d0);
   for (uint32_t f = threadIdx.x; f < F1; f += kThreads) hist[f] = 0;
@@ -223,7 +237,8 @@ __global__ __launch_bounds__(kT1) void k_bq_scatter1(BinnedLaunch A) {
   uint32_t *lstart = hist + F1r;                   // [F1]
   uint32_t *cur = lstart + F1r;                    // [F1]
   uint32_t *part = cur + F1r;                      // [16]
-  const uint32_t j = blockIdx.y, tile = blockIdx.x;
+  uint32_t tile, j;
+  pass1_block(G.n_tiles, tile, j);
   const int64_t d0 = (int64_t)tile * kTileDocs;
   const uint32_t nd = (uint32_t)min((int64_t)kTileDocs, A.n - d0);
   const uint64_t row = ((uint64_t)j * F1) * G.n_tiles + tile;  // + f * n_tiles
