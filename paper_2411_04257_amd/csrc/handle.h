@@ -38,6 +38,7 @@ struct lshbloom {
   uint64_t bin_rec2_cap = 0;    // binned-record slots (records plus pass 2's spare slices)
   uint32_t *d_counts1 = nullptr, *d_bstart = nullptr, *d_off2 = nullptr, *d_end2 = nullptr;
   uint64_t *d_rec1 = nullptr, *d_rec2 = nullptr, *d_bkeys = nullptr, *d_dir = nullptr;
+  uint32_t *d_ovf = nullptr;  // bins left to the general path (count, then bins)
   uint8_t *d_res0 = nullptr;
   int minhash_waves = 0;  // persistent MinHash grid; 0 = sized per call
   int cus = 0;            // compute units of the device

@@ -128,6 +128,7 @@ void free_all(lshbloom *h) {
   if (h->d_off2) (void)hipFree(h->d_off2);
   if (h->d_end2) (void)hipFree(h->d_end2);
   if (h->d_dir) (void)hipFree(h->d_dir);
+  if (h->d_ovf) (void)hipFree(h->d_ovf);
   if (h->d_rec1) (void)hipFree(h->d_rec1);
   if (h->d_rec2) (void)hipFree(h->d_rec2);
   if (h->d_bkeys) (void)hipFree(h->d_bkeys);
@@ -272,6 +273,7 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
                             : 0u;
       }
       a.dir = h->d_dir;
+      a.ovf = h->d_ovf;
       a.res0 = h->d_res0;
       a.flags = d_flags + c0;
       a.status = h->d_status;
@@ -472,7 +474,7 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
     const bool room = prm.chunk_docs || (sliced - records) * 24 + bin_chunk * (24 * probes_per_doc + 9ull * prm.bands) <= budget;
     h->bin_rec2_cap = room && sliced < (1ull << 32) ? sliced : records;
     bin_ws = h->bin_rec2_cap * 24 + bin_chunk * 9ull * prm.bands + h->bin_counts_cap * 4 + h->bin_buckets_cap * 4 +
-             h->bin_bins_cap * 16;
+             h->bin_bins_cap * 20;
   }
   h->bin_chunk = bin_chunk;
   const uint64_t hitb_docs = chunk;
@@ -536,6 +538,7 @@ lshbloom_t *lshbloom_create_ex(const lshbloom_params_t *p) {
     LB_ALLOC(h->d_off2, h->bin_bins_cap * 4);
     LB_ALLOC(h->d_end2, h->bin_bins_cap * 4);
     LB_ALLOC(h->d_dir, h->bin_bins_cap * 8);
+    LB_ALLOC(h->d_ovf, h->bin_bins_cap * 4);
     LB_ALLOC(h->d_rec1, h->bin_rec2_cap * 16);
     LB_ALLOC(h->d_rec2, h->bin_rec2_cap * 8);
     LB_ALLOC(h->d_bkeys, bin_chunk * prm.bands * 8);

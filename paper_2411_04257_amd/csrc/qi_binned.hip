@@ -20,7 +20,8 @@
 //             distinct bits with the least document probing each and a
 //             "probed by two documents or more" flag, ORs every probe into
 //             the words and writes them back with plain stores (it is their
-//             only writer).  A bit
+//             only writer; bins its LDS tables cannot hold are left to
+//             bin_global, in k_bq_bin_overflow).  A bit
 //             was set before document i iff it was set before the chunk or
 //             its least document is < i.  The bin answers that at once for
 //             the probe-0 records (res0), and publishes the bits a later
@@ -68,8 +69,7 @@ __device__ __forceinline__ uint32_t slot_of(uint32_t key, uint32_t cap) {
 // Workgroup barrier for LDS only: waits for this wave's LDS operations, not
 // for its global stores, which stay in flight across the barrier (no kernel
 // here reads back global memory written by another wave of its workgroup
-// except the global-table path of the bin kernel, which uses device-scope
-// atomics and fences).
+// except bin_global, which uses device-scope atomics and fences).
 __device__ __forceinline__ void sync_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Exclusive scan of in[0..n) into out[0..n) (may alias) by a block of NT
@@ -163,6 +163,7 @@ __global__ __launch_bounds__(256) void k_bq_keys(BinnedLaunch A) {
 
 // Zero the probe-0 answers of a chunk (their bytes as 32-bit words).
 __global__ __launch_bounds__(256) void k_bq_zero_res0(BinnedLaunch A, uint64_t words) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) A.ovf[0] = 0;  // no bin left to the general path yet
   uint32_t *w = reinterpret_cast<uint32_t *>(A.res0);
   for (uint64_t q = (uint64_t)blockIdx.x * kThreads + threadIdx.x; q < words; q += (uint64_t)gridDim.x * kThreads)
     w[q] = 0;
@@ -575,6 +576,27 @@ __device__ void bin_global(const BinnedLaunch &A, uint32_t j, uint64_t bin, uint
   wave_sync();
 }
 
+// A bin the wave paths cannot take (more records, shared bits or published
+// bits than their LDS tables hold) is listed for k_bq_bin_overflow, which
+// runs it through bin_global once the bin kernel has ended.  Bins own
+// disjoint filter bits, so the order does not matter; nothing of the bin
+// has been written but probe-0 answers, which bin_global gives again.  Kept
+// out of the bin kernels' loops, the general path leaves their loads and
+// waits as the common path needs them.
+__device__ __forceinline__ void defer_bin(const BinnedLaunch &A, uint64_t bin) {
+  if (threadIdx.x == 0) A.ovf[1 + atomicAdd(&A.ovf[0], 1u)] = (uint32_t)bin;
+}
+
+__global__ __launch_bounds__(64) void k_bq_bin_overflow(BinnedLaunch A) {
+  const BinnedGeometry &G = A.G;
+  for (uint32_t t = blockIdx.x; t < A.ovf[0]; t += gridDim.x) {
+    const uint64_t bin = A.ovf[1 + t];
+    const uint32_t j = (uint32_t)(bin / G.bins_per_band);
+    const uint64_t b0 = (bin - (uint64_t)j * G.bins_per_band) << G.bin_bits;
+    bin_global(A, j, bin, A.off2[bin], A.end2[bin], b0, A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6));
+  }
+}
+
 // Sparse bins (bin_bits > 15: the bin's words do not fit in LDS): one wave
 // per bin (64-thread workgroups), so that a bin's steps need no workgroup
 // barrier and several bins per SIMD overlap their memory latency.  LDS holds,
@@ -595,45 +617,74 @@ __global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
   const uint32_t lane = threadIdx.x;
   const BinnedGeometry &G = A.G;
   const uint64_t n_bins = (uint64_t)A.bands * G.bins_per_band;
-  // The records of the wave's next bin are loaded while it works on the
-  // current one (records of bins above kWCap are not: bin_global reads them).
+  // A wave's bins are pipelined as in the dense kernel: the next bin's
+  // records and the record range of the bin after it are loaded with the
+  // bin's own words and taken in (settle) after its bit table is built,
+  // before any of its stores; every lane loads, the selects come at settle.
   // A bin's records fill rows of 64; in its last row the lanes past the end
   // repeat the bin's first record (a repeated record changes nothing: it
   // finds its bit's slot taken by its twin, ORs the same bit and answers
-  // the same probe 0), so that every lane of a row holds a record.
-  auto load_recs = [&](uint64_t b, uint32_t &q0, uint32_t &q1, uint64_t *out) {
-    q0 = q1 = 0;
-    if (b < n_bins) {
-      q0 = A.off2[b];
-      q1 = A.end2[b];
-    }
-    const uint32_t nrr = q1 - q0;
-    const bool small = nrr <= kWCap;
+  // the same probe 0), so that every lane of a row holds a record; rows
+  // past the end, and every row of a bin above kWCap records, hold ~0.
+  auto load_range = [&](uint64_t b) -> uint32_t {
+    const uint32_t *p = lane == 0 ? A.off2 : A.end2;
+    return p[b < n_bins ? b : 0];
+  };
+  auto range_of = [&](uint32_t v, uint64_t b, uint32_t &q0, uint32_t &q1) {
+    q0 = b < n_bins ? (uint32_t)__builtin_amdgcn_readlane((int)v, 0) : 0u;
+    q1 = b < n_bins ? (uint32_t)__builtin_amdgcn_readlane((int)v, 1) : 0u;
+  };
+  auto load_raw = [&](uint32_t q0, uint32_t q1, uint64_t *raw) {
+    const uint32_t last = q1 > 0 ? q1 - 1 : 0;
 #pragma unroll
     for (uint32_t u = 0; u < kWPer; ++u) {
       const uint32_t r = q0 + u * 64 + lane;
-      out[u] = (small && u * 64 < nrr) ? A.rec2[r < q1 ? r : q0] : ~0ull;
+      raw[u] = A.rec2[min(r < q1 ? r : q0, last)];
     }
   };
-  uint32_t r0, r1;
+  auto mask_recs = [&](uint32_t q0, uint32_t q1, const uint64_t *raw, uint64_t *out) {
+    const uint32_t nrr = q1 - q0;
+    const bool small = nrr <= kWCap;
+#pragma unroll
+    for (uint32_t u = 0; u < kWPer; ++u) out[u] = (small && u * 64 < nrr) ? raw[u] : ~0ull;
+  };
+  uint32_t r0, r1, n0, n1;  // the current and the next bin's record ranges
   uint64_t rec[kWPer];
-  load_recs(blockIdx.x, r0, r1, rec);
+  {
+    const uint64_t b1 = (uint64_t)blockIdx.x + gridDim.x;
+    range_of(load_range(blockIdx.x), blockIdx.x, r0, r1);
+    uint64_t raw[kWPer];
+    load_raw(r0, r1, raw);
+    const uint32_t v1 = load_range(b1);
+    mask_recs(r0, r1, raw, rec);
+    range_of(v1, b1, n0, n1);
+  }
   for (uint64_t bin = blockIdx.x; bin < n_bins; bin += gridDim.x) {
-    const uint64_t nbin = bin + gridDim.x;
-    uint32_t q0, q1;
-    uint64_t nrec[kWPer];
-    const uint32_t nr = r1 - r0;
-    if (nr == 0 || nr > kWCap) {
-      if (nr > kWCap) {
-        const uint32_t j = (uint32_t)(bin / G.bins_per_band);
-        const uint64_t b0 = (bin - (uint64_t)j * G.bins_per_band) << G.bin_bits;
-        bin_global(A, j, bin, r0, r1, b0, A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6));
-      }
-      load_recs(nbin, q0, q1, nrec);
-      r0 = q0;
-      r1 = q1;
+    const uint64_t b2 = bin + 2ull * gridDim.x;
+    uint32_t m0, m1, mv;  // the range of the bin after next
+    uint64_t nraw[kWPer], nrec[kWPer];
+    auto prefetch = [&]() {
+      load_raw(n0, n1, nraw);
+      mv = load_range(b2);
+    };
+    auto settle = [&]() {
+      mask_recs(n0, n1, nraw, nrec);
+      range_of(mv, b2, m0, m1);
+    };
+    auto advance = [&]() {
+      r0 = n0;
+      r1 = n1;
+      n0 = m0;
+      n1 = m1;
 #pragma unroll
       for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
+    };
+    const uint32_t nr = r1 - r0;
+    if (nr == 0 || nr > kWCap) {
+      if (nr > kWCap) defer_bin(A, bin);
+      prefetch();
+      settle();
+      advance();
       continue;
     }
     const uint32_t nu = (nr + 63) >> 6;  // rows of records (uniform)
@@ -652,11 +703,12 @@ __global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
         wv[q] = 0;
       }
     }
-    // this bin's loads first (each record's word), then the next bin's records
+    // this bin's loads first (each record's word; rows past the end re-read
+    // the first record's), then the next bin's records
     uint64_t pre[kWPer];
 #pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) pre[u] = u < nu ? F[(uint32_t)((rec[u] & kMask40) - b0) >> 6] : 0ull;
-    load_recs(nbin, q0, q1, nrec);
+    for (uint32_t u = 0; u < kWPer; ++u) pre[u] = F[(uint32_t)(((u < nu ? rec[u] : rec[0]) & kMask40) - b0) >> 6];
+    prefetch();
     wave_sync();
     // phase A: insert every record's bit into the bit table.  A lane's
     // records probe in rounds (one compare-and-swap per record per round,
@@ -708,6 +760,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
     }
     if (pend) atomicOr(A.status, 4u);  // cannot happen: cap >= distinct bits
     wave_sync();
+    settle();
     // least document (+1) probing each clear bit, 0 for bits set before the
     // chunk (every record of a bit sees the same state)
 #pragma unroll
@@ -803,10 +856,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
     for (uint32_t q = lane; q < pcap; q += 64) T[q] = wv[q];
     if (lane == 0) A.dir[bin] = ((uint64_t)r0 << 32) | pcap;
     wave_sync();
-    r0 = q0;
-    r1 = q1;
-#pragma unroll
-    for (uint32_t u = 0; u < kWPer; ++u) rec[u] = nrec[u];
+    advance();
   }
 }
 
@@ -820,8 +870,8 @@ __global__ __launch_bounds__(64) void k_bq_bin_sparse(BinnedLaunch A) {
 // the chunk or its least document is below i; it is published for the
 // resolve step (by its first claimer) iff it was set before the chunk or two
 // different documents probe it.  The new words are the old words ORed with
-// the claim bitmap.  A list longer than kListCap sends the bin to bin_global
-// (nothing of it has been written yet).
+// the claim bitmap.  A list longer than kListCap leaves the bin to the
+// general path (nothing of it has been written yet).
 #ifndef LB_LIST_CAP
 #define LB_LIST_CAP 96
 #endif
@@ -846,40 +896,78 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
   const uint32_t lane = threadIdx.x;
   const BinnedGeometry &G = A.G;
   const uint64_t n_bins = (uint64_t)A.bands * G.bins_per_band;
-  // The records of the wave's next bin are loaded while it works on the
-  // current one; lanes past the bin's end hold ~0 (not a record: document
-  // indices stay below 2^23 - 1).
-  auto load_recs = [&](uint64_t b, uint32_t &q0, uint32_t &q1, uint64_t *out) {
-    q0 = q1 = 0;
-    if (b < n_bins) {
-      q0 = A.off2[b];
-      q1 = A.end2[b];
-    }
+  // A wave's bins are pipelined: the next bin's records and the record
+  // range of the bin after it are loaded with the bin's own words, and taken
+  // in (settle) after its claims, before any of its stores.  The waits are
+  // then for this bin's loads only: a load behind a branch, or a value used
+  // as soon as it is loaded, would make the wave wait for the words and the
+  // records one after the other.  So every lane loads (lanes past a bin's
+  // end re-read a valid slot) and the selects come at settle, where lanes
+  // past the end get ~0 (not a record: document indices stay below
+  // 2^23 - 1), as does every lane of a bin too large for the dense path.
+  // A range is loaded per lane (its start by lane 0, its end by the others)
+  // so that it stays in a vector register until it is read.
+  auto load_range = [&](uint64_t b) -> uint32_t {
+    const uint32_t *p = lane == 0 ? A.off2 : A.end2;
+    return p[b < n_bins ? b : 0];
+  };
+  auto range_of = [&](uint32_t v, uint64_t b, uint32_t &q0, uint32_t &q1) {
+    q0 = b < n_bins ? (uint32_t)__builtin_amdgcn_readlane((int)v, 0) : 0u;
+    q1 = b < n_bins ? (uint32_t)__builtin_amdgcn_readlane((int)v, 1) : 0u;
+  };
+  auto load_raw = [&](uint32_t q0, uint32_t q1, uint64_t *raw) {
+    const uint32_t last = q1 > 0 ? q1 - 1 : 0;
+#pragma unroll
+    for (uint32_t u = 0; u < kDPer; ++u) raw[u] = A.rec2[min(q0 + u * 64 + lane, last)];
+  };
+  auto mask_recs = [&](uint32_t q0, uint32_t q1, const uint64_t *raw, uint64_t *out) {
     const bool small = q1 - q0 <= kDCap;
 #pragma unroll
     for (uint32_t u = 0; u < kDPer; ++u) {
       const uint32_t r = q0 + u * 64 + lane;
-      out[u] = (small && r < q1) ? A.rec2[r] : ~0ull;
+      out[u] = (small && r < q1) ? raw[u] : ~0ull;
     }
   };
-  uint32_t r0, r1;
+  uint32_t r0, r1, n0, n1;  // the current and the next bin's record ranges
   uint64_t rec[kDPer];
-  load_recs(blockIdx.x, r0, r1, rec);
+  {
+    const uint64_t b1 = (uint64_t)blockIdx.x + gridDim.x;
+    range_of(load_range(blockIdx.x), blockIdx.x, r0, r1);
+    uint64_t raw[kDPer];
+    load_raw(r0, r1, raw);
+    const uint32_t v1 = load_range(b1);
+    mask_recs(r0, r1, raw, rec);
+    range_of(v1, b1, n0, n1);
+  }
   for (uint64_t bin = blockIdx.x; bin < n_bins; bin += gridDim.x) {
-    const uint64_t nbin = bin + gridDim.x;
-    uint32_t q0, q1;
-    uint64_t nrec[kDPer];
+    const uint64_t b2 = bin + 2ull * gridDim.x;
+    uint32_t m0, m1, mv;  // the range of the bin after next
+    uint64_t nraw[kDPer], nrec[kDPer];
+    auto prefetch = [&]() {
+      load_raw(n0, n1, nraw);
+      mv = load_range(b2);
+    };
+    auto settle = [&]() {
+      mask_recs(n0, n1, nraw, nrec);
+      range_of(mv, b2, m0, m1);
+    };
+    auto advance = [&]() {
+      r0 = n0;
+      r1 = n1;
+      n0 = m0;
+      n1 = m1;
+#pragma unroll
+      for (uint32_t u = 0; u < kDPer; ++u) rec[u] = nrec[u];
+    };
     const uint32_t nr = r1 - r0;
     const uint32_t j = (uint32_t)(bin / G.bins_per_band);
     const uint64_t b0 = (bin - (uint64_t)j * G.bins_per_band) << G.bin_bits;  // a multiple of 64
     uint64_t *F = A.filters + (uint64_t)j * A.words_per_band + (b0 >> 6);
     if (nr == 0 || nr > kDCap) {
-      if (nr > kDCap) bin_global(A, j, bin, r0, r1, b0, F);
-      load_recs(nbin, q0, q1, nrec);
-      r0 = q0;
-      r1 = q1;
-#pragma unroll
-      for (uint32_t u = 0; u < kDPer; ++u) rec[u] = nrec[u];
+      if (nr > kDCap) defer_bin(A, bin);
+      prefetch();
+      settle();
+      advance();
       continue;
     }
     // the bin's words: 2^(bin_bits - 6) <= kWRegion, fewer in a band's last bin
@@ -896,11 +984,14 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
 #pragma unroll
       for (uint32_t u = 0; u < kWRegion / 64; ++u) {
         const uint32_t w = u * 64 + lane;
-        reg[u] = (full || w < W) ? F[w] : 0ull;
+        reg[u] = F[full ? w : min(w, W - 1)];
       }
-      load_recs(nbin, q0, q1, nrec);
+      prefetch();
 #pragma unroll
-      for (uint32_t u = 0; u < kWRegion / 64; ++u) wv[u * 64 + lane] = reg[u];
+      for (uint32_t u = 0; u < kWRegion / 64; ++u) {
+        const uint32_t w = u * 64 + lane;
+        wv[w] = (full || w < W) ? reg[u] : 0ull;
+      }
     }
     wave_sync();
     // claims: one atomicOr per record; later claimers list their bit
@@ -930,14 +1021,12 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
       }
     }
     wave_sync();
+    settle();
     const uint32_t nl = ln;
     if (nl > kListCap) {
       // more shared bits than the list holds: the general path
-      bin_global(A, j, bin, r0, r1, b0, F);
-      r0 = q0;
-      r1 = q1;
-#pragma unroll
-      for (uint32_t u = 0; u < kDPer; ++u) rec[u] = nrec[u];
+      defer_bin(A, bin);
+      advance();
       continue;
     }
     // records of listed bits: the first list entry of their bit, and the
@@ -990,11 +1079,8 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
       // more bits to publish than the LDS table holds (a filter nearly full):
       // the general path; nothing of the bin but probe-0 answers, which it
       // gives again, has been written
-      bin_global(A, j, bin, r0, r1, b0, F);
-      r0 = q0;
-      r1 = q1;
-#pragma unroll
-      for (uint32_t u = 0; u < kDPer; ++u) rec[u] = nrec[u];
+      defer_bin(A, bin);
+      advance();
       continue;
     }
     const uint32_t pcap = min(2 * mine, kWRegion);
@@ -1025,10 +1111,7 @@ __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
     for (uint32_t q = lane; q < pcap; q += 64) T[q] = wv[q];
     if (lane == 0) A.dir[bin] = ((uint64_t)r0 << 32) | pcap;
     wave_sync();
-    r0 = q0;
-    r1 = q1;
-#pragma unroll
-    for (uint32_t u = 0; u < kDPer; ++u) rec[u] = nrec[u];
+    advance();
   }
 }
 
@@ -1210,6 +1293,10 @@ hipError_t launch_bins(const BinnedLaunch &a, hipStream_t s) {
     hipLaunchKernelGGL(k_bq_bin_dense, dim3(gb), dim3(64), 0, s, a);
   else
     hipLaunchKernelGGL(k_bq_bin_sparse, dim3(gb), dim3(64), 0, s, a);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // the bins left to the general path (usually none: then every wave reads
+  // the count and ends)
+  hipLaunchKernelGGL(k_bq_bin_overflow, dim3((unsigned)kDenseWavesPerCu * (a.cus ? a.cus : 256)), dim3(64), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   // slices of bands per document: enough threads for about 2^18 (document,
   // slice) pairs, at most one band per slice and 256 slices
