@@ -77,6 +77,8 @@ hipError_t finish_qi(lshbloom *h, hipStream_t s);
 // part 0 enqueues the whole query-insert; when qi_splits(h, n), part 1
 // enqueues its partition passes and part 2 the rest (1 then 2 on one stream
 // is the whole call); otherwise part 1 enqueues everything and part 2 nothing.
+// Parts 1 and 2 are the batched form's, whose next MinHash runs beside them:
+// they size the dense bins' persistent grid to leave it room.
 int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n, uint8_t *d_flags, hipStream_t s,
                const uint64_t *d_keys = nullptr, int part = 0);
 // The query-insert of n documents is one binned chunk (so it splits in two).

@@ -231,6 +231,8 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
   hipError_t e;
   const uint64_t pd = (uint64_t)h->prm.bands * h->k;
   const bool binned = h->bin_chunk && (h->qi_mode == 2 || (h->qi_mode == 0 && n_docs >= kBinnedMinDocs));
+  // parts are enqueued by the batched form, whose next MinHash runs beside them
+  const bool shared_device = part != 0;
   if (part != 0 && !qi_splits(h, n_docs)) {
     if (part == 2) return LSHBLOOM_OK;
     part = 0;
@@ -278,6 +280,7 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
       a.flags = d_flags + c0;
       a.status = h->d_status;
       a.cus = (uint32_t)h->cus;
+      a.shared_device = shared_device;
       if (lb::binned_counts_entries(G, h->prm.bands) > h->bin_counts_cap ||
           lb::binned_bucket_entries(G, h->prm.bands) > h->bin_buckets_cap ||
           lb::binned_bin_entries(G, h->prm.bands) > h->bin_bins_cap) {

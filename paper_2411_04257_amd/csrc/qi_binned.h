@@ -57,6 +57,7 @@ struct BinnedLaunch {
   uint8_t *flags;      // [n]
   uint32_t *status;
   uint32_t cus;        // compute units of the device (sizes persistent grids)
+  bool shared_device;  // other kernels run beside this call's (the batched form's next MinHash)
 };
 
 // Spare slots per bin for pass 2's single-read layout: about five standard

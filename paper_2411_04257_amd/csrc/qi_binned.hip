@@ -881,11 +881,18 @@ constexpr uint32_t kListCap = LB_LIST_CAP;
 constexpr uint32_t kDPer = 9;
 constexpr uint32_t kDCap = kDPer * 64;
 static_assert(kDPer <= 32, "per-lane record masks are 32-bit");
-// Persistent grid of the dense bin kernel, waves per compute unit.
+// Persistent grid of the dense bin kernel, waves per compute unit: 16 when
+// the call has the device to itself (LDS holds 17 waves of 9.1 KB), 12 when
+// other kernels run beside it (the batched form's next MinHash), which keeps
+// room on every SIMD for one of their waves.
 #ifndef LB_DENSE_WPC
-#define LB_DENSE_WPC 12
+#define LB_DENSE_WPC 16
+#endif
+#ifndef LB_DENSE_WPC_SHARED
+#define LB_DENSE_WPC_SHARED 12
 #endif
 constexpr uint32_t kDenseWavesPerCu = LB_DENSE_WPC;
+constexpr uint32_t kDenseWavesPerCuShared = LB_DENSE_WPC_SHARED;
 
 __global__ __launch_bounds__(64) void k_bq_bin_dense(BinnedLaunch A) {
   __shared__ __align__(16) unsigned long long wv[kWRegion];  // the bin's words; then its published table
@@ -1284,10 +1291,12 @@ hipError_t launch_bins(const BinnedLaunch &a, hipStream_t s) {
   hipError_t e;
   const uint64_t n_bins = (uint64_t)a.bands * G.bins_per_band;
   // dense bins: a persistent grid of kDenseWavesPerCu waves per compute unit,
-  // which leaves room on every compute unit for the waves of a MinHash launch
-  // running beside it; sparse bins: one workgroup per bin (at most 262,144),
-  // as many waves as fit, to cover the random reads' latency
-  const uint64_t cap = G.direct_words ? (uint64_t)kDenseWavesPerCu * (a.cus ? a.cus : 256) : 262144;
+  // or of kDenseWavesPerCuShared beside other work, which leaves room on every
+  // compute unit for the waves of a MinHash launch; sparse bins: one
+  // workgroup per bin (at most 262,144), as many waves as fit, to cover the
+  // random reads' latency
+  const uint32_t wpc = a.shared_device ? kDenseWavesPerCuShared : kDenseWavesPerCu;
+  const uint64_t cap = G.direct_words ? (uint64_t)wpc * (a.cus ? a.cus : 256) : 262144;
   const unsigned gb = (unsigned)(n_bins < cap ? n_bins : cap);
   if (G.direct_words)
     hipLaunchKernelGGL(k_bq_bin_dense, dim3(gb), dim3(64), 0, s, a);
