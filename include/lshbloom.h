@@ -133,6 +133,9 @@ typedef struct lshbloom_info {
   uint64_t seed;
   int poisoned;
   uint32_t device_status; /* 0 unless a kernel detected an internal inconsistency */
+  uint64_t general_path_bins; /* binned query-insert: bins whose records or bits outgrew the
+                                 one-wave LDS tables and took the global-memory path, summed
+                                 over the handle's calls (a diagnostic; results are the same) */
 } lshbloom_info_t;
 
 /* Create an index of `bands` empty Bloom filters (Section 4: one per band)

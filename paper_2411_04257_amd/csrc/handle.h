@@ -24,7 +24,7 @@ struct lshbloom {
   uint64_t *d_keys = nullptr;
   uint64_t *d_masks = nullptr;
   uint8_t *d_hitb = nullptr;
-  uint32_t *d_status = nullptr;
+  uint32_t *d_status = nullptr;  // [0]: consistency word; bytes 8..15: bins left to the binned path's general path
   uint32_t *h_status = nullptr;  // pinned host copy of d_status, refreshed at the end of every query-insert call
   uint64_t *d_count = nullptr;  // per-band set-bit counts [bands]
   uint64_t chunk_docs = 0;

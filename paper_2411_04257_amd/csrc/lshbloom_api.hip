@@ -276,6 +276,7 @@ int qi_enqueue(lshbloom *h, const uint32_t *d_sigs, int64_t n_docs, uint8_t *d_f
       }
       a.dir = h->d_dir;
       a.ovf = h->d_ovf;
+      a.ovf_total = reinterpret_cast<unsigned long long *>(h->d_status + 2);
       a.res0 = h->d_res0;
       a.flags = d_flags + c0;
       a.status = h->d_status;
@@ -1072,6 +1073,9 @@ int lshbloom_info(const lshbloom_t *hc, lshbloom_info_t *out) {
   uint32_t st = 0;
   if (hipMemcpy(&st, hm->d_status, sizeof st, hipMemcpyDeviceToHost) != hipSuccess) st = 0xFFFFFFFFu;
   out->device_status = st;
+  uint64_t gp = 0;
+  if (hipMemcpy(&gp, hm->d_status + 2, sizeof gp, hipMemcpyDeviceToHost) != hipSuccess) gp = ~0ull;
+  out->general_path_bins = gp;
   return LSHBLOOM_OK;
 }
 

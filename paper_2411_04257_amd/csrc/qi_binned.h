@@ -53,6 +53,7 @@ struct BinnedLaunch {
   uint32_t slice_slack; // spare slots per bin of pass 2's slices (0: counted, compact layout)
   uint64_t *dir;       // [bands * bins_per_band] published table of a bin: first record << 32 | slots
   uint32_t *ovf;       // [1 + bands * bins_per_band] count, then the bins left to the general path
+  unsigned long long *ovf_total;  // bins left to the general path, summed over chunks (a diagnostic)
   uint8_t *res0;       // [bands][n] probe 0 of (document, band) was set before the document
   uint8_t *flags;      // [n]
   uint32_t *status;

@@ -589,6 +589,7 @@ __device__ __forceinline__ void defer_bin(const BinnedLaunch &A, uint64_t bin) {
 
 __global__ __launch_bounds__(64) void k_bq_bin_overflow(BinnedLaunch A) {
   const BinnedGeometry &G = A.G;
+  if (blockIdx.x == 0 && threadIdx.x == 0 && A.ovf[0]) atomicAdd(A.ovf_total, (unsigned long long)A.ovf[0]);
   for (uint32_t t = blockIdx.x; t < A.ovf[0]; t += gridDim.x) {
     const uint64_t bin = A.ovf[1 + t];
     const uint32_t j = (uint32_t)(bin / G.bins_per_band);

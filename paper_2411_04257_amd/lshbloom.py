@@ -64,6 +64,7 @@ class Info(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("poisoned", ctypes.c_int),
         ("device_status", ctypes.c_uint32),
+        ("general_path_bins", ctypes.c_uint64),
     ]
 
 

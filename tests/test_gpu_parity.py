@@ -186,7 +186,10 @@ def _random_sigs(rng, n, P):
     return rng.integers(0, 2**32, (n, P), dtype=np.uint64).astype(np.uint32)
 
 
-def _qi_case(gpu, sigs, chunk_docs=0, batches=None, qi_mode=0, **kw):
+def _qi_case(gpu, sigs, chunk_docs=0, batches=None, qi_mode=0, general=None, **kw):
+    """Flags and filters of a query-insert equal the oracle's.  With
+    `general` and the binned path, whether some bin took the global-memory
+    path (its records or bits outgrew a wave's LDS tables) is checked too."""
     P = sigs.shape[1]
     g, o = _pair(gpu, num_perm=P, chunk_docs=chunk_docs, qi_mode=qi_mode, **kw)
     want = o.query_insert(sigs)
@@ -201,7 +204,10 @@ def _qi_case(gpu, sigs, chunk_docs=0, batches=None, qi_mode=0, **kw):
         got = torch.cat(parts).cpu().numpy()
     np.testing.assert_array_equal(got, want)
     np.testing.assert_array_equal(g.read_filters().cpu().numpy().view(np.uint64), o.filters())
-    assert g.info()["device_status"] == 0
+    inf = g.info()
+    assert inf["device_status"] == 0
+    if general is not None and qi_mode == 2:
+        assert (inf["general_path_bins"] > 0) == general, inf["general_path_bins"]
     g.close()
     return want
 
@@ -210,7 +216,7 @@ def _qi_case(gpu, sigs, chunk_docs=0, batches=None, qi_mode=0, **kw):
 def test_query_insert_identical_documents(gpu, qi_mode):
     rng = np.random.default_rng(1)
     sigs = np.repeat(_random_sigs(rng, 1, 128), 5000, axis=0)
-    want = _qi_case(gpu, sigs, qi_mode=qi_mode)
+    want = _qi_case(gpu, sigs, qi_mode=qi_mode, general=True)
     assert want[0] == 0 and want[1:].all()
 
 
@@ -278,7 +284,7 @@ def test_query_insert_sparse_bins_with_repeats(gpu, qi_mode):
         s = int(rng.integers(max(0, i - 3000), i))
         j = int(rng.integers(0, 16))
         sigs[i, j * r:(j + 1) * r] = sigs[s, j * r:(j + 1) * r]
-    want = _qi_case(gpu, sigs, chunk_docs=2500, n=10_000_000, fp=1e-5, qi_mode=qi_mode)
+    want = _qi_case(gpu, sigs, chunk_docs=2500, n=10_000_000, fp=1e-5, qi_mode=qi_mode, general=False)
     assert want[rep].all()
 
 
@@ -289,7 +295,7 @@ def test_query_insert_identical_documents_sparse_bins(gpu, qi_mode):
     rng = np.random.default_rng(24)
     sigs = np.concatenate([_random_sigs(rng, 500, 128), np.repeat(_random_sigs(rng, 1, 128), 3000, axis=0),
                            _random_sigs(rng, 500, 128)])
-    want = _qi_case(gpu, sigs, n=10_000_000, fp=1e-5, qi_mode=qi_mode)
+    want = _qi_case(gpu, sigs, n=10_000_000, fp=1e-5, qi_mode=qi_mode, general=True)
     assert want[501:3500].all() and not want[500]
 
 
@@ -325,6 +331,7 @@ def test_query_insert_dense_bins_over_saturated_filters(gpu):
     np.testing.assert_array_equal(got, want)
     np.testing.assert_array_equal(g.read_filters().cpu().numpy().view(np.uint64), o.filters())
     assert g.info()["device_status"] == 0
+    assert g.info()["general_path_bins"] > 0
     assert 0.9 < want.mean() < 1.0
     g.close()
 
