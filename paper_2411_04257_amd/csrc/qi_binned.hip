@@ -238,6 +238,7 @@ __global__ __launch_bounds__(kT1) void k_bq_scatter1(BinnedLaunch A) {
   uint32_t *lstart = hist + F1r;                   // [F1]
   uint32_t *cur = lstart + F1r;                    // [F1]
   uint32_t *part = cur + F1r;                      // [16]
+  uint32_t *dl = part + 16;                        // [F1] where a bucket's run goes, less its stage start
   uint32_t tile, j;
   pass1_block(G.n_tiles, tile, j);
   const int64_t d0 = (int64_t)tile * kTileDocs;
@@ -278,16 +279,17 @@ __global__ __launch_bounds__(kT1) void k_bq_scatter1(BinnedLaunch A) {
 #pragma unroll
     for (uint32_t u = 0; u < kPer1; ++u)
       if (rec[u] != ~0ull) stage[lstart[(uint32_t)((rec[u] & kMask40) >> G.bucket_bits)] + rk[u]] = rec[u];
+    // stage slot p of bucket f goes to p + dl[f] (one LDS read per record);
+    // the bucket's write position moves past this sub-tile's share
+    for (uint32_t f = threadIdx.x; f < F1; f += kT1) {
+      dl[f] = cur[f] - lstart[f];
+      cur[f] += hist[f];
+      hist[f] = 0;
+    }
     sync_lds();
     for (uint32_t p = threadIdx.x; p < cnt; p += kT1) {
       const uint64_t r = stage[p];
-      const uint32_t f = (uint32_t)((r & kMask40) >> G.bucket_bits);
-      A.rec1[cur[f] + (p - lstart[f])] = r;
-    }
-    sync_lds();
-    for (uint32_t f = threadIdx.x; f < F1; f += kT1) {
-      cur[f] += hist[f];
-      hist[f] = 0;
+      A.rec1[p + dl[(uint32_t)((r & kMask40) >> G.bucket_bits)]] = r;
     }
     sync_lds();
   }
@@ -349,6 +351,7 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
   uint32_t *lstart = h + F2;                     // [F2]
   uint32_t *part = lstart + F2;                  // [16]
   uint32_t *ovf = part + 16;                     // [1] a bin outgrew its slice
+  uint32_t *dl = ovf + 1;                        // [F2] where a bin's run goes, less its stage start
 
   const uint32_t q = blockIdx.x;
   const uint32_t j = q / G.buckets_per_band, f = q - j * G.buckets_per_band;
@@ -387,6 +390,13 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
 #pragma unroll
       for (uint32_t u = 0; u < kPer2; ++u)
         if (rec[u] != ~0ull) stage[lstart[((uint32_t)rec[u] >> G.bin_bits) & bmask] + rk[u]] = rec[u];
+      // stage slot p of bin b goes to p + dl[b]; the bin's write position
+      // moves past this sub-tile's share
+      for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
+        dl[b] = cur[b] - lstart[b];
+        cur[b] += h[b];
+        h[b] = 0;
+      }
 #pragma unroll
       for (uint32_t u = 0; u < kPer2; ++u) {
         const uint32_t r = q0 + kSub2 + u * kT2 + threadIdx.x;
@@ -396,16 +406,11 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
       for (uint32_t p = threadIdx.x; p < cnt; p += kT2) {
         const uint64_t r = stage[p];
         const uint32_t b = ((uint32_t)r >> G.bin_bits) & bmask;
-        const uint32_t w = cur[b] + (p - lstart[b]);
+        const uint32_t w = p + dl[b];
         if (!limit || w < base2 + (b + 1) * capb)
           A.rec2[w] = r;
         else
           *ovf = 1u;
-      }
-      sync_lds();
-      for (uint32_t b = threadIdx.x; b < F2; b += kT2) {
-        cur[b] += h[b];
-        h[b] = 0;
       }
       sync_lds();
     }
@@ -1278,10 +1283,10 @@ hipError_t launch_partition(const BinnedLaunch &a, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_bq_scan_buckets, dim3(1), dim3(kThreads), 0, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds1 = kSub1 * 8 + 3 * (size_t)((G.buckets_per_band + 3) & ~3u) * 4 + 16 * 4;
+  const size_t lds1 = kSub1 * 8 + 4 * (size_t)((G.buckets_per_band + 3) & ~3u) * 4 + 16 * 4;
   hipLaunchKernelGGL(k_bq_scatter1, dim3(G.n_tiles, a.bands), dim3(kT1), lds1, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds2 = kSub2 * 8 + 3 * (size_t)G.bins_per_bucket * 4 + 17 * 4;
+  const size_t lds2 = kSub2 * 8 + 4 * (size_t)G.bins_per_bucket * 4 + 17 * 4;
   hipLaunchKernelGGL(k_bq_part2, dim3(nb), dim3(kT2), lds2, s, a);
   return hipGetLastError();
 }
