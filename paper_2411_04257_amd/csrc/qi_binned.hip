@@ -190,15 +190,11 @@ constexpr uint32_t kT1 = kTileDocs;
 constexpr uint32_t kPer1 = LB_PER1;
 constexpr uint32_t kSub1 = kT1 * kPer1;
 
-// Pass-1 blocks, renumbered so that each of the 8 XCDs (which take the
-// launch's blocks in turn) works through a contiguous range of (band, tile)
-// pairs: neighbouring tiles' writes to a bucket, whose ends share lines, then
-// meet in one L2.
+// Pass-1 blocks, renumbered so that each of the 8 XCDs works through a
+// contiguous range of (band, tile) pairs: neighbouring tiles' writes to a
+// bucket, whose ends share lines, then meet in one L2.
 __device__ __forceinline__ void pass1_block(uint32_t n_tiles, uint32_t &tile, uint32_t &band) {
-  const uint32_t total = gridDim.x * gridDim.y;
-  const uint32_t L = blockIdx.x + gridDim.x * blockIdx.y;
-  const uint32_t x = L & 7u, i = L >> 3, q = total >> 3, r = total & 7u;
-  const uint32_t P = x * q + min(x, r) + i;
+  const uint32_t P = xcd_contiguous(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);
   tile = P % n_tiles;
   band = P / n_tiles;
 }

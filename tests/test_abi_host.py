@@ -125,6 +125,7 @@ uint32_t h_shingle5(const uint32_t* t) { return lb::shingle_hash_fixed<5>(t); }
 uint32_t h_shingle(const uint32_t* t, uint32_t n) { return lb::shingle_hash_var(t, n); }
 uint64_t h_band_key(const uint32_t* row, uint32_t r, uint64_t salt) { return lb::band_key(row, r, salt); }
 uint64_t h_mulhi(uint64_t a, uint64_t b) { return lb::umulhi64(a, b); }
+uint32_t h_xcd(uint32_t L, uint32_t total) { return lb::xcd_contiguous(L, total); }
 }
 """
 
@@ -152,6 +153,8 @@ def harness(tmp_path_factory):
     L.h_band_key.restype = ctypes.c_uint64
     L.h_mulhi.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
     L.h_mulhi.restype = ctypes.c_uint64
+    L.h_xcd.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    L.h_xcd.restype = ctypes.c_uint32
     return L
 
 
@@ -231,3 +234,19 @@ def test_device_band_key_and_mulhi(harness):
         assert harness.h_band_key(row.ctypes.data, r, salt) == oracle.band_key(row, 0, r, salt)
         a, b = int(rng.integers(0, 2**64, dtype=np.uint64)), int(rng.integers(0, 2**64, dtype=np.uint64))
         assert harness.h_mulhi(a, b) == (a * b) >> 64
+
+
+def test_xcd_contiguous_launch_order(harness):
+    """Pass-1 workgroups are renumbered for the 8 XCDs (workgroup L runs on
+    XCD L mod 8): every number in [0, total) is taken exactly once, and each
+    XCD's workgroups, in launch order, take consecutive numbers, XCD 0 the
+    lowest.  Launch sizes of one to a few tiles per band, and the 1M- and
+    2M-document chunks of 32 bands."""
+    for total in list(range(1, 70)) + [9 * 65, 977 * 32, 1954 * 32]:
+        P = [harness.h_xcd(L, total) for L in range(total)]
+        assert sorted(P) == list(range(total))
+        lo = 0
+        for x in range(8):
+            mine = [P[L] for L in range(x, total, 8)]
+            assert mine == list(range(lo, lo + len(mine)))
+            lo += len(mine)
