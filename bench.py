@@ -73,7 +73,7 @@ def qi_traffic(key: str):
     a plain copy), for the kernel version built here and the workload and
     batch size `key` names ("<workload>_b<documents per batch>"); None
     otherwise."""
-    rows = profile_rows("query_insert_counters.md", source_tag("qi_binned.hip", "qi_binned.h", "device_math.h"))
+    rows = profile_rows("query_insert_counters.md", source_tag("qi_binned.hip", "qi_binned.h", "device_math.h", "launch_order.h"))
     r = rows.get(key)
     return None if r is None else r[0] + r[1]
 

@@ -318,14 +318,4 @@ LB_FN uint64_t band_key(const uint32_t *row0, uint32_t rows, uint64_t salt_m) {
   return K;
 }
 
-// Launch order.  The device hands a launch's workgroups to its 8 XCDs in
-// turn (workgroup L to XCD L mod 8).  xcd_contiguous(L, total) renumbers them
-// so that each XCD takes a contiguous, ordered range of [0, total): XCD x
-// holds floor(total / 8) numbers, one more if x < total mod 8, after those of
-// XCDs 0..x-1.  A bijection of [0, total).
-LB_FN uint32_t xcd_contiguous(uint32_t L, uint32_t total) {
-  const uint32_t x = L & 7u, i = L >> 3, q = total >> 3, r = total & 7u;
-  return x * q + (x < r ? x : r) + i;
-}
-
 }  // namespace lb

@@ -41,6 +41,7 @@
 #include <algorithm>
 
 #include "device_math.h"
+#include "launch_order.h"
 #include "qi_binned.h"
 
 namespace lb {

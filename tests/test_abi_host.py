@@ -111,6 +111,7 @@ def test_optimal_bands_agree_with_oracle():
 
 _HARNESS = r"""
 #include "device_math.h"
+#include "launch_order.h"
 extern "C" {
 uint32_t h_perm(uint32_t x, uint64_t a, uint64_t b) {
   return lb::perm_lo32(x, (uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
