@@ -13,8 +13,10 @@
 //             into buckets of consecutive bins, staging each 16,384-record
 //             sub-tile in LDS so that every bucket's records leave as one
 //             contiguous run; each XCD takes a contiguous range of tiles;
-//   pass 2    (k_bq_part2): one block per bucket counts its bins, publishes
-//             their record ranges and splits the bucket the same way;
+//   pass 2    (k_bq_part2): one block per bucket splits it into its bins
+//             the same way (large buckets straight into per-bin slices,
+//             smaller ones after counting their bins) and publishes each
+//             bin's record range;
 //   bins      (k_bq_bin): one wave per bin reads the bin's filter words
 //             (the state before the chunk), builds in LDS a table of its
 //             distinct bits with the least document probing each and a
