@@ -317,9 +317,10 @@ __global__ __launch_bounds__(256) void k_bq_scan_buckets(BinnedLaunch A) {
 
 // ---------------------------------------------------------------- pass 2 ----
 // One 1024-thread block per bucket (one block fills a compute unit's LDS)
-// splits the bucket into bins through LDS-staged sub-tiles of 16,384
-// records, so that each bin's share of a sub-tile leaves as one contiguous
-// run, and publishes every bin's record range [start, end).
+// splits the bucket into bins through LDS-staged sub-tiles of PER x 1024
+// records (19 where LDS holds them beside the bins' arrays, up to 507 bins
+// per bucket, else 16), so that each bin's share of a sub-tile leaves as one
+// contiguous run, and publishes every bin's record range [start, end).
 //
 // Bucket q owns the binned-record region that starts at bstart[q] +
 // q (slack + 1) F2 and holds its T records plus (slack + 1) F2 spare slots.
@@ -336,11 +337,18 @@ __global__ __launch_bounds__(256) void k_bq_scan_buckets(BinnedLaunch A) {
 #ifndef LB_PER2
 #define LB_PER2 16
 #endif
+#ifndef LB_PER2_BIG
+#define LB_PER2_BIG 19
+#endif
 constexpr uint32_t kT2 = LB_T2;
 constexpr uint32_t kPer2 = LB_PER2;
-constexpr uint32_t kSub2 = kT2 * kPer2;
+constexpr uint32_t kPer2Big = LB_PER2_BIG;
+// LDS of a pass-2 block: the stage, four per-bin arrays, 17 more words
+constexpr size_t part2_lds(uint32_t per, uint32_t bins) { return (size_t)per * kT2 * 8 + 4 * (size_t)bins * 4 + 17 * 4; }
 
+template <uint32_t PER>
 __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
+  constexpr uint32_t kSub2 = kT2 * PER;
   extern __shared__ __align__(16) uint8_t smem[];
   const BinnedGeometry &G = A.G;
   const uint32_t F2 = G.bins_per_bucket;
@@ -370,24 +378,24 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
   // sub-tile (loaded here unless `loaded`); the next sub-tile's records are
   // loaded as soon as the current ones sit in LDS, so that their latency
   // overlaps the write-out and the barriers.
-  uint64_t rec[kPer2];
+  uint64_t rec[PER];
   auto split = [&](bool limit, bool loaded) {
     if (!loaded) {
 #pragma unroll
-      for (uint32_t u = 0; u < kPer2; ++u) {
+      for (uint32_t u = 0; u < PER; ++u) {
         const uint32_t r = s0 + u * kT2 + threadIdx.x;
         rec[u] = r < s1 ? A.rec1[r] : ~0ull;
       }
     }
     for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
-      uint32_t rk[kPer2];
+      uint32_t rk[PER];
 #pragma unroll
-      for (uint32_t u = 0; u < kPer2; ++u)
+      for (uint32_t u = 0; u < PER; ++u)
         if (rec[u] != ~0ull) rk[u] = atomicAdd(&h[((uint32_t)rec[u] >> G.bin_bits) & bmask], 1u);
       sync_lds();
       const uint32_t cnt = block_scan<kT2>(h, lstart, F2, part);
 #pragma unroll
-      for (uint32_t u = 0; u < kPer2; ++u)
+      for (uint32_t u = 0; u < PER; ++u)
         if (rec[u] != ~0ull) stage[lstart[((uint32_t)rec[u] >> G.bin_bits) & bmask] + rk[u]] = rec[u];
       // stage slot p of bin b goes to p + dl[b]; the bin's write position
       // moves past this sub-tile's share
@@ -397,7 +405,7 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
         h[b] = 0;
       }
 #pragma unroll
-      for (uint32_t u = 0; u < kPer2; ++u) {
+      for (uint32_t u = 0; u < PER; ++u) {
         const uint32_t r = q0 + kSub2 + u * kT2 + threadIdx.x;
         rec[u] = r < s1 ? A.rec1[r] : ~0ull;
       }
@@ -442,25 +450,25 @@ __global__ __launch_bounds__(kT2) void k_bq_part2(BinnedLaunch A) {
     // (bucket_bits <= 32 is checked at launch), so the later sub-tiles load
     // only those
     const uint32_t *lo1 = reinterpret_cast<const uint32_t *>(A.rec1);
-    uint32_t bi[kPer2];
+    uint32_t bi[PER];
 #pragma unroll
-    for (uint32_t u = 0; u < kPer2; ++u) {
+    for (uint32_t u = 0; u < PER; ++u) {
       const uint32_t r = s0 + u * kT2 + threadIdx.x;
       rec[u] = r < s1 ? A.rec1[r] : ~0ull;
       bi[u] = r < s1 ? ((uint32_t)rec[u] >> G.bin_bits) & bmask : ~0u;
     }
     for (uint32_t q0 = s0; q0 < s1; q0 += kSub2) {
-      uint32_t g[kPer2];
+      uint32_t g[PER];
 #pragma unroll
-      for (uint32_t u = 0; u < kPer2; ++u) {
+      for (uint32_t u = 0; u < PER; ++u) {
         const uint32_t r = q0 + kSub2 + u * kT2 + threadIdx.x;
         g[u] = r < s1 ? lo1[2ull * r] : 0u;
       }
 #pragma unroll
-      for (uint32_t u = 0; u < kPer2; ++u)
+      for (uint32_t u = 0; u < PER; ++u)
         if (bi[u] != ~0u) atomicAdd(&cur[bi[u]], 1u);
 #pragma unroll
-      for (uint32_t u = 0; u < kPer2; ++u)
+      for (uint32_t u = 0; u < PER; ++u)
         bi[u] = q0 + kSub2 + u * kT2 + threadIdx.x < s1 ? (g[u] >> G.bin_bits) & bmask : ~0u;
     }
     loaded = true;
@@ -1285,8 +1293,12 @@ hipError_t launch_partition(const BinnedLaunch &a, hipStream_t s) {
   const size_t lds1 = kSub1 * 8 + 4 * (size_t)((G.buckets_per_band + 3) & ~3u) * 4 + 16 * 4;
   hipLaunchKernelGGL(k_bq_scatter1, dim3(G.n_tiles, a.bands), dim3(kT1), lds1, s, a);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  const size_t lds2 = kSub2 * 8 + 4 * (size_t)G.bins_per_bucket * 4 + 17 * 4;
-  hipLaunchKernelGGL(k_bq_part2, dim3(nb), dim3(kT2), lds2, s, a);
+  // the larger sub-tile where LDS holds it (c3: 118,000-record buckets in 7
+  // sub-tiles instead of 8; c4: a larger first sub-tile kept in registers)
+  if (part2_lds(kPer2Big, G.bins_per_bucket) <= 163840)
+    hipLaunchKernelGGL(k_bq_part2<kPer2Big>, dim3(nb), dim3(kT2), part2_lds(kPer2Big, G.bins_per_bucket), s, a);
+  else
+    hipLaunchKernelGGL(k_bq_part2<kPer2>, dim3(nb), dim3(kT2), part2_lds(kPer2, G.bins_per_bucket), s, a);
   return hipGetLastError();
 }
 
